@@ -1,0 +1,191 @@
+/*
+ * libhweno -- MI355X (gfx950) implementation of the fifth-order finite volume
+ * derivative-based Hermite WENO scheme with unified stencils (Chen & Zhao)
+ * and its SSP-RK3 time stepping, for u_t + div F(u) = 0, u(x,0) = u0(x)
+ * (Sec. 1, eq. hyperbolic-conservation-laws) on uniform 1D and 2D meshes.
+ *
+ * The library evolves, per cell, the average u-bar and the derivative
+ * averages of every conserved component (Sec. 2.1: v-bar = mean of u_x;
+ * Sec. 2.2: scaled averages v-bar = (1/dy) int u_x, w-bar = (1/dx) int u_y).
+ * One handle holds one or many independent problems (same dimension, flux
+ * family and configuration; any sizes, domains, boundaries and end times);
+ * every RK stage of every problem of a handle is one kernel launch.
+ *
+ * Conventions for every call:
+ *   - Returns HWENO_OK (0) or a negative HWENO_ERR_* status; never aborts.
+ *     hweno_last_error() then describes the failure.
+ *   - All work is ordered on the HIP stream given to hweno_create.  Calls
+ *     marked "synchronising" wait for that stream before returning; the
+ *     others only enqueue, and device-side failures (non-admissible states)
+ *     surface at the next synchronising call.
+ *   - Host pointers are plain C arrays owned by the caller; "on_device"
+ *     arguments select device pointers (also owned by the caller) instead.
+ *   - State arrays at the boundary are always double precision with the
+ *     layout  state[((var*K + comp)*ny + j)*nx + i],  var 0 = u-bar,
+ *     1 = v-bar, 2 = w-bar (2D); K = 1 (scalar), 3 (1D Euler: rho, rho*mu, E)
+ *     or 4 (2D Euler: rho, rho*mu, rho*nu, E); ny = 1 in 1D.
+ */
+#ifndef HWENO_H
+#define HWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hweno_handle hweno_handle; /* opaque; owns what it allocates */
+
+enum {
+    HWENO_OK = 0,
+    HWENO_ERR_ARG = -1,       /* invalid argument or configuration            */
+    HWENO_ERR_NONFINITE = -2, /* non-finite value, or rho <= 0 / p <= 0        */
+    HWENO_ERR_HIP = -3,       /* a HIP runtime call failed                     */
+    HWENO_ERR_STATE = -4,     /* call out of order (e.g. step before set_state)*/
+    HWENO_ERR_OOM = -5        /* device memory or workspace too small          */
+};
+
+/* Flux families (Sec. 3: Burgers, Examples 1 and 3; Euler, Examples 2 and 4;
+ * linear advection f = a u, g = b u). */
+enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 };
+
+/* Boundary treatment per axis: periodic wrap, or transmissive (every unknown
+ * of the ghost cells copied from the nearest interior cell). */
+enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1 };
+
+/* Arithmetic of the path:
+ *   F64       everything in double precision;
+ *   F32       state and arithmetic in single precision (time step in double);
+ *   F32_ACC64 single-precision reconstruction and fluxes, cell averages kept
+ *             and updated in double, flux differences taken in double;
+ *   F32_KAHAN single-precision everything, cell averages kept as a
+ *             compensated (hi, lo) single-precision pair. */
+enum { HWENO_F64 = 0, HWENO_F32 = 1, HWENO_F32_ACC64 = 2, HWENO_F32_KAHAN = 3 };
+
+/* Nonlinear weights w~_m = gamma_m (1 + tau^2 / D_m), w = w~ / sum w~:
+ *   W_PAPER  D_m = beta_m + eps in 1D (eq. nonlinear-weights) and
+ *            beta_m^2 + eps in 2D (eq. nonlinear-weights-2D), as printed;
+ *   W_BETA   D_m = beta_m + eps in both dimensions (the default: the form
+ *            that reproduces the paper's Tables 1 and 3);
+ *   W_BETA2  D_m = beta_m^2 + eps in both dimensions;
+ *   W_LINEAR w_m = gamma_m (the linear scheme; for tests). */
+enum { HWENO_W_PAPER = 0, HWENO_W_BETA = 1, HWENO_W_BETA2 = 2, HWENO_W_LINEAR = 3 };
+
+typedef struct {
+    int32_t dim;          /* 1 or 2                                        */
+    int32_t flux;         /* HWENO_ADVECTION / HWENO_BURGERS / HWENO_EULER */
+    int32_t nx, ny;       /* cells; nx >= 4, ny >= 4 in 2D, ny = 1 in 1D    */
+    double xlo, xhi, ylo, yhi; /* domain [xlo,xhi] x [ylo,yhi]             */
+    int32_t bc_x, bc_y;   /* HWENO_PERIODIC / HWENO_TRANSMISSIVE           */
+    double gas_gamma;     /* ratio of specific heats (Euler), e.g. 1.4      */
+    double adv[2];        /* advection velocity (a, b)                      */
+    double t_end;         /* final time used by hweno_run_to_time           */
+} hweno_problem;
+
+typedef struct {
+    int32_t precision;    /* HWENO_F64 ... HWENO_F32_KAHAN                 */
+    int32_t gauss_q;      /* Gauss points per edge in 2D: 2 or 3           */
+    int32_t weights;      /* HWENO_W_*                                      */
+    double gamma_lin[5];  /* linear weights gamma_0..gamma_M, M = 2 (1D) or
+                             4 (2D); positive, summing to one (eq. rewrite,
+                             eq. rewrite-2D)                                */
+    double eps;           /* epsilon of the weights (1e-8 in the paper)    */
+    double cfl;           /* CFL number (0.6 in the paper's tests)         */
+    double dt_exponent;   /* 1: dt = cfl*dx/alpha (1D), cfl/(ax/dx+ay/dy)
+                             (2D); e != 1 uses dx^e, dy^e (5/3 for the
+                             accuracy runs of Sec. 3.1)                    */
+} hweno_config;
+
+/* Fills cfg with the paper's settings for dimension dim: gamma = 1/400 per
+ * linear polynomial and the rest on p0 (Sec. 3), eps = 1e-8, CFL 0.6, Q = 3,
+ * W_BETA, F64, dt_exponent 1. */
+void hweno_default_config(int32_t dim, hweno_config* cfg);
+
+/* Bytes of device memory hweno_create needs for these problems, so that a
+ * caller can provide them as one workspace (e.g. a torch uint8 tensor).
+ * Returns 0 on invalid arguments. */
+size_t hweno_workspace_bytes(const hweno_problem* probs, int32_t nprob,
+                             const hweno_config* cfg);
+
+/* Creates a handle for nprob problems (all of the same dim and flux).
+ * workspace: device memory of at least hweno_workspace_bytes() bytes that the
+ * handle uses for all its buffers (it stays owned by the caller and must
+ * outlive the handle), or NULL to let the handle allocate its own.
+ * hip_stream: the hipStream_t every call is ordered on (NULL = null stream).
+ * Errors: ERR_ARG (mismatched dims or flux, nx/ny out of range, gauss_q not
+ * 2 or 3, linear weights not all positive or |sum - 1| > 1e-12, eps <= 0,
+ * cfl <= 0), ERR_OOM, ERR_HIP. */
+int hweno_create(const hweno_problem* probs, int32_t nprob, const hweno_config* cfg,
+                 void* workspace, size_t ws_bytes, void* hip_stream, hweno_handle** out);
+
+/* Uploads the state of problem prob (layout above, double) and sets its time
+ * to t.  Synchronising.  Errors: ERR_ARG (bad prob index or NULL src). */
+int hweno_set_state(hweno_handle* h, int32_t prob, const double* src,
+                    int32_t src_on_device, double t);
+
+/* Downloads the state of problem prob (layout above, double) and its time.
+ * Synchronising; reports a pending ERR_NONFINITE first. */
+int hweno_get_state(hweno_handle* h, int32_t prob, double* dst, int32_t dst_on_device,
+                    double* t);
+
+/* The semi-discrete operator of eq. semi-discrete-scheme (1D) or
+ * eq. 2D-semi-discrete-scheme-uniform (2D), L(U) = (L^u, L^v[, L^w]), and the
+ * modified state U-hat = (u-bar, v-hat[, w-hat]) of Step 3, for the current
+ * state of problem prob, with the global Lax-Friedrichs speeds taken from its
+ * current cell averages.  Both outputs have the state layout (double).
+ * Either may be NULL.  Synchronising.  Does not change the state. */
+int hweno_rhs(hweno_handle* h, int32_t prob, double* L_out, double* Uhat_out,
+              int32_t on_device);
+
+/* Lax-Friedrichs speeds (alpha_x, alpha_y) of the current cell averages of
+ * problem prob: max |f'(u)| (Euler: |velocity| + sound speed) over its cells.
+ * Synchronising.  Errors: ERR_NONFINITE if a cell is not admissible. */
+int hweno_alpha(hweno_handle* h, int32_t prob, double* ax, double* ay);
+
+/* One SSP-RK3 step (Sec. 2.1 Step 4, Sec. 2.2 Step 4) of every problem that
+ * has not reached its t_end.  dt_in: NULL for the CFL rule (alpha from the
+ * step's initial cell averages, last step clipped onto t_end), or a host
+ * array of nprob time steps (a problem's step is still clipped onto t_end;
+ * a value <= 0 skips the problem).  dt_out: NULL, or a host array of nprob
+ * doubles receiving the steps taken (then the call synchronises).
+ * Otherwise the call only enqueues. Errors: ERR_STATE before set_state. */
+int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out);
+
+/* Advances every problem to its t_end with the CFL rule.  Synchronising.
+ * steps_out (may be NULL) receives the number of steps of the longest run.
+ * Errors: ERR_NONFINITE (names the problem and cell), ERR_STATE. */
+int hweno_run_to_time(hweno_handle* h, int64_t* steps_out);
+
+/* Waits for the handle's stream and reports a pending device-side error. */
+int hweno_sync(hweno_handle* h);
+
+/* Kernel tiling of the stage kernels.  tile_rows: rows one workgroup
+ * marches through in 2D (8..1024) or cells per tile in 1D (fixed by the
+ * kernel, ignored); grid_blocks: workgroups of the persistent launch (0 =
+ * one per tile); use_graph: capture one step as a HIP graph (1) or launch
+ * eagerly (0).  Changing any of these never changes a result bit. */
+typedef struct {
+    int32_t tile_rows;
+    int32_t grid_blocks;
+    int32_t use_graph;
+    int32_t reserved;
+} hweno_tuning;
+
+int hweno_get_tuning(const hweno_handle* h, hweno_tuning* t);
+int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
+
+/* Times candidate tilings on the handle's current state (which it restores)
+ * and keeps the fastest.  Synchronising.  best (may be NULL) receives it. */
+int hweno_autotune(hweno_handle* h, hweno_tuning* best);
+
+int hweno_destroy(hweno_handle* h);
+
+/* Text of the last error on h, or of the last failed hweno_create on this
+ * thread when h is NULL.  Never NULL. */
+const char* hweno_last_error(const hweno_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HWENO_H */

@@ -1,0 +1,337 @@
+"""Pins of the oracle's whole scheme: fluxes, the semi-discrete operator on
+tiny grids against a brute-force restatement, invariants (constant states,
+conservation, symmetries), fifth-order convergence and the paper's accuracy
+tables (Sec. 3.1, Tables 1-4)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import bruteforce as BF
+from paper_2607_24325_amd import workloads as W
+
+RNG = np.random.default_rng(2024)
+
+
+def oproblem(spec, **kw):
+    """oracle problem for a workload spec"""
+    d = dict(dim=spec.dim, flux=spec.flux, nx=spec.nx, ny=spec.ny, xlo=spec.xlo,
+             xhi=spec.xhi, ylo=spec.ylo, yhi=spec.yhi, bc_x=spec.bc_x, bc_y=spec.bc_y,
+             gas_gamma=spec.gas_gamma, adv=spec.adv, weights=O.W_BETA)
+    d.update(kw)
+    return O.Problem(**d)
+
+
+# ------------------------------------------------------------- fluxes -----
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_euler_jacobian_vector_products_match_finite_differences(dim):
+    """h = f'(u) v for the Euler system (Examples 2 and 4): the oracle's
+    Jacobian-vector product equals a central difference of its flux."""
+    p = O.Problem(dim=dim, flux=O.EULER, nx=8, ny=1 if dim == 1 else 8)
+    for _ in range(10):
+        if dim == 1:
+            U = W.conserved_1d(RNG.uniform(0.2, 2), RNG.uniform(-1, 1), RNG.uniform(0.2, 2))
+        else:
+            U = W.conserved_2d(RNG.uniform(0.2, 2), RNG.uniform(-1, 1), RNG.uniform(-1, 1),
+                               RNG.uniform(0.2, 2))
+        V = RNG.normal(size=U.size)
+        for d in range(dim):
+            _, jv = O.flux(p, d, U, V)
+            h = 1e-6
+            fp, _ = O.flux(p, d, U + h * V)
+            fm, _ = O.flux(p, d, U - h * V)
+            np.testing.assert_allclose(jv, (fp - fm) / (2 * h), rtol=1e-7, atol=1e-8)
+
+
+def test_euler_flux_values():
+    """Euler flux of Example 2 at a hand-computed state."""
+    p = O.Problem(dim=1, flux=O.EULER, nx=8)
+    rho, u, pr = 2.0, 3.0, 5.0
+    U = W.conserved_1d(rho, u, pr)
+    f, _ = O.flux(p, 0, U)
+    E = pr / 0.4 + 0.5 * rho * u * u
+    np.testing.assert_allclose(f, [rho * u, rho * u * u + pr, u * (E + pr)], rtol=1e-15)
+
+
+# ----------------------------------------------------- brute force --------
+
+@pytest.mark.parametrize("flux", ["burgers", "advection"])
+@pytest.mark.parametrize("weights", [O.W_BETA, O.W_BETA2])
+def test_1d_operator_matches_brute_force(flux, weights):
+    n, dx = 7, 0.31
+    ub = 0.5 + RNG.normal(size=n)
+    vb = RNG.normal(size=n)
+    p = O.Problem(dim=1, flux=O.BURGERS if flux == "burgers" else O.ADVECTION, nx=n,
+                  xlo=0, xhi=n * dx, adv=(1.3, 0.0), weights=weights)
+    st = np.zeros(p.shape())
+    st[0, 0, 0], st[1, 0, 0] = ub, vb
+    alpha = 2.5
+    L, Uh = O.rhs(p, st, alpha)
+    if flux == "burgers":
+        f, df = (lambda u: 0.5 * u * u), (lambda u: u)
+    else:
+        f, df = (lambda u: 1.3 * u), (lambda u: 1.3)
+    Lu, Lv, vh = BF.rhs_1d_scalar(ub, vb, dx, f, df, alpha, p.gamma_lin, p.eps,
+                                  squared=weights == O.W_BETA2)
+    np.testing.assert_allclose(L[0, 0, 0], Lu, rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(L[1, 0, 0], Lv, rtol=1e-11, atol=1e-11)
+    np.testing.assert_allclose(Uh[1, 0, 0], vh, rtol=1e-11, atol=1e-11)
+    np.testing.assert_array_equal(Uh[0, 0, 0], ub)
+
+
+@pytest.mark.parametrize("Q", [2, 3])
+@pytest.mark.parametrize("weights", [O.W_BETA, O.W_BETA2])
+def test_2d_operator_matches_brute_force(Q, weights):
+    nx = ny = 5
+    dx, dy = 0.4, 0.3
+    ub = 0.5 + RNG.normal(size=(ny, nx))
+    vb = RNG.normal(size=(ny, nx))
+    wb = RNG.normal(size=(ny, nx))
+    p = O.Problem(dim=2, flux=O.BURGERS, nx=nx, ny=ny, xlo=0, xhi=nx * dx, ylo=0,
+                  yhi=ny * dy, gauss_q=Q, weights=weights)
+    st = np.zeros(p.shape())
+    st[0, 0], st[1, 0], st[2, 0] = ub, vb, wb
+    ax, ay = 2.1, 1.7
+    L, Uh = O.rhs(p, st, ax, ay)
+    Lu, Lv, Lw, vh, wh = BF.rhs_2d_scalar(ub, vb, wb, dx, dy, lambda u: 0.5 * u * u,
+                                          lambda u: u, ax, ay, p.gamma_lin, p.eps,
+                                          weights == O.W_BETA2, Q)
+    for a, b in ((L[0, 0], Lu), (L[1, 0], Lv), (L[2, 0], Lw), (Uh[1, 0], vh), (Uh[2, 0], wh)):
+        np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-10)
+
+
+# ----------------------------------------------------------- invariants ---
+
+CASES = [
+    lambda: W.burgers_1d(24),
+    lambda: W.euler_1d_smooth(24),
+    lambda: W.riemann_1d(3, nx=32),
+    lambda: W.burgers_2d(8),
+    lambda: W.euler_2d_smooth(8),
+    lambda: W.quadrant_vortex_2d(16, seed=7),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_constant_state_is_preserved(case):
+    spec, st = CASES[case]()
+    const = np.zeros_like(st)
+    const[0] = st[0].mean(axis=(1, 2), keepdims=True)   # constant averages, zero slopes
+    p = oproblem(spec, gauss_q=2)
+    ax, ay = O.alpha(p, const)
+    L, Uh = O.rhs(p, const, ax, ay)
+    assert not L.any()                      # identical fluxes on every face
+    # modified derivatives vanish up to the rounding of the printed sums
+    np.testing.assert_allclose(Uh, const, rtol=0, atol=1e-15 * np.abs(const).max())
+    out = O.step(p, const, ax, ay, 0.01)
+    # only the convex combinations of SSP-RK3 round (e.g. u/3 + 2u/3)
+    np.testing.assert_allclose(out, const, rtol=4e-16, atol=1e-15 * np.abs(const).max())
+
+
+@pytest.mark.parametrize("case", [0, 1, 3, 4])
+def test_periodic_conservation(case):
+    """The scheme is conservative (eq. semi-discrete-scheme): on a periodic grid
+    the total of each component's cell averages stays fixed to roundoff."""
+    spec, st = CASES[case]()
+    p = oproblem(spec, gauss_q=2)
+    tot0 = st[0].sum(axis=(1, 2))
+    cur = st
+    for _ in range(10):
+        ax, ay = O.alpha(p, cur)
+        cur = O.step(p, cur, ax, ay, 0.5 * O.dt(p, ax, ay, 0.6))
+    tot = cur[0].sum(axis=(1, 2))
+    scale = np.abs(st[0]).max() * spec.ncells
+    assert np.all(np.abs(tot - tot0) <= 64 * 1e-16 * scale)
+
+
+def test_1d_mirror_symmetry():
+    """x -> -x maps the scheme onto itself: averages mirror, derivative means
+    change sign; for Euler the momentum changes sign too."""
+    spec, st = W.riemann_1d(5, nx=40)
+    p = oproblem(spec)
+    mir = st[:, :, :, ::-1].copy()
+    mir[1] *= -1.0
+    mir[:, 1] *= -1.0          # momentum component
+    ax, _ = O.alpha(p, st)
+    a = O.step(p, st, ax, 0, 1e-3)
+    b = O.step(p, mir, ax, 0, 1e-3)
+    bm = b[:, :, :, ::-1].copy()
+    bm[1] *= -1.0
+    bm[:, 1] *= -1.0
+    np.testing.assert_allclose(a, bm, rtol=1e-13, atol=1e-13)
+
+
+def test_2d_transpose_symmetry():
+    """On a square grid swapping x and y (and v-bar with w-bar, and the two
+    momenta) commutes with one step."""
+    spec, st = W.quadrant_vortex_2d(16, seed=3)
+    p = oproblem(spec, gauss_q=2)
+    tr = np.swapaxes(st, 2, 3).copy()
+    tr[[1, 2]] = tr[[2, 1]]
+    tr[:, [1, 2]] = tr[:, [2, 1]]
+    ax, ay = O.alpha(p, st)
+    a = O.step(p, st, ax, ay, 1e-3)
+    b = O.step(p, tr, ay, ax, 1e-3)
+    bt = np.swapaxes(b, 2, 3).copy()
+    bt[[1, 2]] = bt[[2, 1]]
+    bt[:, [1, 2]] = bt[:, [2, 1]]
+    np.testing.assert_allclose(a, bt, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_window_step_equals_full_step(dim):
+    """Single cells of a step computed on a local window equal the full-grid
+    step (used to check sampled cells of very large grids)."""
+    if dim == 1:
+        spec, st = W.riemann_1d(2, nx=64)
+        p = oproblem(spec)
+        win = [(0, 0, 5, 1), (30, 0, 4, 1), (60, 0, 4, 1)]
+    else:
+        spec, st = W.quadrant_vortex_2d(24, seed=9)
+        p = oproblem(spec, gauss_q=2, bc_x=O.TRANSMISSIVE)
+        win = [(0, 0, 3, 3), (10, 20, 4, 4), (21, 5, 3, 2)]
+    ax, ay = O.alpha(p, st)
+    full = O.step(p, st, ax, ay, 2e-3)
+    Lf, Uf = O.rhs(p, st, ax, ay)
+    for (i0, j0, wi, wj) in win:
+        w = O.step_window(p, st, ax, ay, 2e-3, i0, j0, wi, wj)
+        np.testing.assert_array_equal(w, full[:, :, j0:j0 + w.shape[2], i0:i0 + wi])
+        Lw, Uw = O.rhs_window(p, st, ax, ay, i0, j0, wi, wj)
+        np.testing.assert_array_equal(Lw, Lf[:, :, j0:j0 + w.shape[2], i0:i0 + wi])
+        np.testing.assert_array_equal(Uw, Uf[:, :, j0:j0 + w.shape[2], i0:i0 + wi])
+
+
+# ------------------------------------------------------ convergence -------
+
+def _advection_l1(n, exponent, gam):
+    spec, st = W.advection_1d(n)
+    p = oproblem(spec, gamma_lin=gam)
+    out, steps = O.run(p, st, 0.0, 2.0, 0.6, exponent)
+    _, exact = W.advection_1d(n)    # period 2: exact solution = initial data
+    return np.abs(out[0, 0, 0] - exact[0, 0, 0]).mean(), steps
+
+
+@pytest.mark.parametrize("gam", [(0.98, 0.01, 0.01), (0.995, 0.0025, 0.0025)])
+def test_fifth_order_on_smooth_advection(gam):
+    """u_t + u_x = 0, u0 = 1 + 0.5 sin(pi x), T = 2, N = 50..400 with
+    dt ~ dx^(5/3): observed L1 order ~ 5 for any positive linear weights."""
+    errs = [(n, _advection_l1(n, 5.0 / 3.0, gam)[0]) for n in (50, 100, 200, 400)]
+    orders = [np.log(e0 / e1) / np.log(n1 / n0) for (n0, e0), (n1, e1) in zip(errs, errs[1:])]
+    assert all(4.6 < o < 5.6 for o in orders[1:]), orders
+
+
+def test_advection_headline_case_with_cfl_time_step():
+    """N = 200, dt = 0.6 dx: 334 steps including the clipped last one; the
+    error is dominated by the third-order time error (documented)."""
+    l1, steps = _advection_l1(200, 1.0, (0.98, 0.01, 0.01))
+    assert steps == 334
+    assert 1e-8 < l1 < 1e-6
+
+
+# ------------------------------------------------------- paper tables -----
+
+def _burgers_exact_avg(nx, t, nq=10):
+    dx = 2.0 / nx
+    g, w = np.polynomial.legendre.leggauss(nq)
+    g, w = 0.5 * (g + 1), 0.5 * w
+    avg = np.zeros(nx)
+    for gq, wq in zip(g, w):
+        x = dx * (np.arange(nx) + gq)
+        xi = x.copy()
+        for _ in range(80):   # characteristics: x = xi + u0(xi) t
+            xi -= (xi + (0.5 + np.sin(np.pi * xi)) * t - x) / (1 + np.pi * np.cos(np.pi * xi) * t)
+        avg += wq * (0.5 + np.sin(np.pi * xi))
+    return avg
+
+
+TABLE1 = {40: (2.66e-05, 1.39e-04), 80: (3.65e-07, 4.32e-06), 120: (4.64e-08, 6.02e-07),
+          160: (1.08e-08, 1.44e-07), 200: (3.57e-09, 4.72e-08), 240: (1.44e-09, 1.90e-08)}
+
+
+def test_table1_burgers_1d():
+    """Example 1 / Table 1 (HWENO rows): with L1 = mean over cells of the
+    cell-average error and dt = 0.6 dx^(5/3) / alpha, the oracle reproduces
+    the printed errors within 15% for N >= 80 and the orders within 0.2."""
+    res = {}
+    for n in TABLE1:
+        spec, st = W.burgers_1d(n)
+        p = oproblem(spec)
+        out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
+        e = np.abs(out[0, 0, 0] - _burgers_exact_avg(n, spec.t_end))
+        res[n] = (e.mean(), e.max())
+    for n in (80, 120, 160, 200, 240):
+        for k in (0, 1):
+            assert 0.85 < res[n][k] / TABLE1[n][k] < 1.1, (n, k, res[n][k], TABLE1[n][k])
+    ns = sorted(TABLE1)
+    for a, b in zip(ns[1:], ns[2:]):
+        ours = np.log(res[a][0] / res[b][0]) / np.log(b / a)
+        paper = np.log(TABLE1[a][0] / TABLE1[b][0]) / np.log(b / a)
+        assert abs(ours - paper) < 0.2, (a, b, ours, paper)
+
+
+def test_table1_rejects_first_order_time_step():
+    """With dt proportional to dx the N = 240 error is two orders of magnitude
+    above Table 1: the accuracy tables used dt ~ dx^(5/3)."""
+    spec, st = W.burgers_1d(240)
+    p = oproblem(spec)
+    out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 1.0)
+    e = np.abs(out[0, 0, 0] - _burgers_exact_avg(240, spec.t_end)).mean()
+    assert e > 50 * TABLE1[240][0]
+
+
+TABLE2 = {40: (5.20e-07, 1.97e-06), 80: (1.62e-08, 3.27e-08)}
+
+
+def test_table2_euler_1d_weak():
+    """Example 2 / Table 2: density L1 within 10% (a weak pin: the paper's
+    Euler runs may have been characteristic-wise, ours is component-wise)."""
+    for n, (l1, _) in TABLE2.items():
+        spec, st = W.euler_1d_smooth(n)
+        p = oproblem(spec)
+        out, _ = O.run(p, st, 0.0, 2.0, 0.6, 5.0 / 3.0)
+        dx = spec.dx
+        xl = dx * np.arange(n)
+        ex = 1 + 0.2 * (np.cos(np.pi * (xl - 2)) - np.cos(np.pi * (xl + dx - 2))) / (np.pi * dx)
+        e = np.abs(out[0, 0, 0] - ex).mean()
+        assert 0.9 < e / l1 < 1.1, (n, e, l1)
+
+
+def _burgers2d_exact_avg(n, t, nq=6):
+    dx = 4.0 / n
+    g, w = np.polynomial.legendre.leggauss(nq)
+    g, w = 0.5 * (g + 1), 0.5 * w
+    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    avg = np.zeros((n, n))
+    for a in range(nq):
+        for b in range(nq):
+            s = (I + g[a]) * dx + (J + g[b]) * dx
+            xi = s.copy()
+            for _ in range(60):   # u = u0(s - 2 u t), s = x + y
+                xi -= (xi + 2 * (0.5 + np.sin(0.5 * np.pi * xi)) * t - s) / \
+                      (1 + np.pi * np.cos(0.5 * np.pi * xi) * t)
+            avg += w[a] * w[b] * (0.5 + np.sin(0.5 * np.pi * xi))
+    return avg
+
+
+TABLE3 = {40: (3.87e-05, 2.51e-04), 80: (1.13e-06, 1.33e-05)}
+
+
+def test_table3_burgers_2d_selects_the_weight_form():
+    """Example 3 / Table 3 with Q = 3: the weights gamma (1 + tau^2/(beta+eps))
+    reproduce the printed errors within 10%, while the printed 2D form
+    beta^2 + eps is far off on the 40 x 40 mesh."""
+    O.set_threads(4)
+    try:
+        for n, (l1, li) in TABLE3.items():
+            spec, st = W.burgers_2d(n)
+            p = oproblem(spec, gauss_q=3, weights=O.W_BETA)
+            out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
+            e = np.abs(out[0, 0] - _burgers2d_exact_avg(n, spec.t_end))
+            assert 0.9 < e.mean() / l1 < 1.1 and 0.9 < e.max() / li < 1.1, (n, e.mean(), e.max())
+        spec, st = W.burgers_2d(40)
+        p = oproblem(spec, gauss_q=3, weights=O.W_BETA2)
+        out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
+        e = np.abs(out[0, 0] - _burgers2d_exact_avg(40, spec.t_end))
+        assert e.mean() > 10 * TABLE3[40][0]
+    finally:
+        O.set_threads(0)
