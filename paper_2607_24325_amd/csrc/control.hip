@@ -1,0 +1,233 @@
+// Per-step control kernels: wave-speed reduction for the global
+// Lax-Friedrichs flux and the CFL rule, time-step selection, time update,
+// and conversion between the boundary layout and the internal planes.
+#include "device_common.h"
+
+namespace hweno {
+
+// Zeroes the wave-speed maxima of every problem and the step counters.
+__global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) {
+        probs[p].ax_bits = 0;
+        probs[p].ay_bits = 0;
+    }
+    if (p == 0) {
+        ctl->nactive = 0;
+        ctl->step_active = 0;
+    }
+}
+
+template <class T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ long long wave_min_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// alpha_x = max |f'(u)|, alpha_y = max |g'(u)| over the cell averages of a
+// problem (Euler: |velocity| + sound speed), in double precision; cells that
+// are not finite or have rho <= 0 / p <= 0 flag the problem.
+template <int P, int FLUX, int DIM>
+__global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* probs,
+                                                    const Chunk* chunks, int nchunks,
+                                                    Scheme sch, int all_problems) {
+    using TU = typename PrecT<P>::TU;
+    constexpr int K = FLUX == F_EULER ? (DIM == 1 ? 3 : 4) : 1;
+    __shared__ double smx[4], smy[4];
+    __shared__ long long sbad[4];
+    const TU* U = (const TU*)uptr;
+    const double g = sch.gas_gamma;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const Chunk chunk = chunks[ch];
+        ProbDev& P_ = probs[chunk.prob];
+        if (!all_problems && (!(P_.t < P_.t_end) || P_.err)) continue;
+        const int64_t plane = (int64_t)P_.nx * P_.ny;
+        const TU* base = U + P_.off_u;
+        double mx = 0.0, my = 0.0;
+        long long bad = LLONG_MAX;
+        for (int k = threadIdx.x; k < chunk.count; k += 256) {
+            const int64_t idx = chunk.start + k;
+            double u[K];
+            bool ok = true;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                u[c] = (double)base[c * plane + idx];
+                ok = ok && isfinite(u[c]);
+            }
+            double sx = 0.0, sy = 0.0;
+            if (FLUX == F_ADV) {
+                sx = fabs(sch.adv[0]);
+                sy = fabs(sch.adv[1]);
+            } else if (FLUX == F_BURGERS) {
+                sx = sy = fabs(u[0]);
+            } else {
+                const double rho = u[0];
+                const double vx = u[1] / rho;
+                const double vy = DIM == 2 ? u[2] / rho : 0.0;
+                const double ke = 0.5 * rho * (vx * vx + vy * vy);
+                const double pr = (g - 1.0) * (u[K - 1] - ke);
+                ok = ok && rho > 0.0 && pr > 0.0;
+                const double cs = ok ? sqrt(g * pr / rho) : 0.0;
+                sx = fabs(vx) + cs;
+                sy = fabs(vy) + cs;
+            }
+            if (ok) {
+                mx = fmax(mx, sx);
+                my = fmax(my, sy);
+            } else if (idx < bad) {
+                bad = idx;
+            }
+        }
+        mx = wave_max(mx);
+        my = wave_max(my);
+        bad = wave_min_ll(bad);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            smx[wv] = mx;
+            smy[wv] = my;
+            sbad[wv] = bad;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w) {
+                mx = fmax(mx, smx[w]);
+                my = fmax(my, smy[w]);
+                bad = sbad[w] < bad ? sbad[w] : bad;
+            }
+            // non-negative doubles order like their bit patterns
+            atomicMax((unsigned long long*)&P_.ax_bits, (unsigned long long)__double_as_longlong(mx));
+            atomicMax((unsigned long long*)&P_.ay_bits, (unsigned long long)__double_as_longlong(my));
+            if (bad != LLONG_MAX) {
+                atomicMin((long long*)&P_.bad_cell, bad);
+                atomicOr(&P_.err, 1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// dt = min(CFL rule, t_end - t); the CFL rule is cfl*dx^e/alpha_x in 1D and
+// cfl/(alpha_x/dx^e + alpha_y/dy^e) in 2D (or the caller's step).
+__global__ void dt_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    ProbDev& P_ = probs[p];
+    P_.active = 0;
+    P_.last = 0;
+    P_.dt = 0.0;
+    if (!(P_.t < P_.t_end) || P_.err) return;
+    double dtc;
+    if (use_dt_in) {
+        dtc = P_.dt_in;
+        if (!(dtc > 0.0)) return;
+    } else {
+        const double ax = as_double(P_.ax_bits), ay = as_double(P_.ay_bits);
+        dtc = ctl->dim == 1 ? ctl->cfl * P_.dxe / ax : ctl->cfl / (ax / P_.dxe + ay / P_.dye);
+    }
+    const double rem = P_.t_end - P_.t;
+    const int last = !(dtc < rem);
+    P_.dt = last ? rem : dtc;
+    P_.last = last;
+    P_.active = 1;
+    atomicOr(&ctl->step_active, 1);
+}
+
+// t += dt (exactly t_end on the clipped last step); counts problems still
+// running and the steps in which anything advanced.
+__global__ void finish_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) {
+        ProbDev& P_ = probs[p];
+        if (P_.active) P_.t = P_.last ? P_.t_end : P_.t + P_.dt;
+        if (P_.t < P_.t_end && !P_.err) atomicAdd(&ctl->nactive, 1);
+    }
+    if (p == 0 && ctl->step_active) ctl->steps += 1;
+}
+
+template <class TU, class TD>
+__global__ void pack_kernel(int to_internal, double* ext, TU* u, TD* d, int K, int nvar,
+                            int64_t ncell) {
+    const int64_t n = (int64_t)nvar * K * ncell;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t plane = e / ncell;   // var*K + comp
+        const int64_t cell = e - plane * ncell;
+        if (plane < K) {
+            if (to_internal) u[e] = (TU)ext[e];
+            else ext[e] = (double)u[e];
+        } else {
+            const int64_t de = (plane - K) * ncell + cell;
+            if (to_internal) d[de] = (TD)ext[e];
+            else ext[e] = (double)d[de];
+        }
+    }
+}
+
+// --------------------------------------------------------------- launchers
+
+hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s) {
+    reset_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t alpha_dispatch(int flux, int dim, const void* u, ProbDev* probs,
+                                 const Chunk* chunks, int nchunks, const Scheme& sch, int all,
+                                 int grid, hipStream_t s) {
+    if (dim == 1) {
+        if (flux == F_ADV) alpha_kernel<P, F_ADV, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        else alpha_kernel<P, F_EULER, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+    } else {
+        if (flux == F_ADV) alpha_kernel<P, F_ADV, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        else alpha_kernel<P, F_EULER, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* probs,
+                        const Chunk* chunks, int nchunks, const Scheme& sch, int all_problems,
+                        int grid, hipStream_t s) {
+    if (grid <= 0 || grid > nchunks) grid = nchunks;
+    if (prec == P_F32) return alpha_dispatch<P_F32>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
+    return alpha_dispatch<P_F64>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
+}
+
+hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, hipStream_t s) {
+    dt_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, use_dt_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s) {
+    finish_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(int prec, int to_internal, double* ext, StateBuf buf, int64_t off_u,
+                       int64_t off_d, int K, int nvar, int64_t ncell, hipStream_t s) {
+    const int64_t n = (int64_t)nvar * K * ncell;
+    const int grid = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (prec == P_F64) {
+        pack_kernel<double, double><<<grid, 256, 0, s>>>(to_internal, ext, (double*)buf.u + off_u,
+                                                         (double*)buf.d + off_d, K, nvar, ncell);
+    } else if (prec == P_F32) {
+        pack_kernel<float, float><<<grid, 256, 0, s>>>(to_internal, ext, (float*)buf.u + off_u,
+                                                       (float*)buf.d + off_d, K, nvar, ncell);
+    } else {
+        pack_kernel<double, float><<<grid, 256, 0, s>>>(to_internal, ext, (double*)buf.u + off_u,
+                                                        (float*)buf.d + off_d, K, nvar, ncell);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace hweno

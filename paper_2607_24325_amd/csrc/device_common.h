@@ -1,0 +1,159 @@
+// Device-side building blocks of the HWENO stage kernels (gfx950, wave64):
+// precision policies, boundary index maps, physical fluxes and their
+// Jacobian-vector products, and the nonlinear weights.
+#pragma once
+
+#include "internal.h"
+
+namespace hweno {
+
+// ---------------------------------------------------------------- types ----
+
+// TU: storage of cell averages; TD: storage of derivative averages;
+// T: reconstruction / flux arithmetic; TA: arithmetic of the cell-average
+// update (flux differences and the RK combination of u-bar).
+template <int P> struct PrecT;
+template <> struct PrecT<P_F64> { using TU = double; using TD = double; using T = double; using TA = double; };
+template <> struct PrecT<P_F32> { using TU = float;  using TD = float;  using T = float;  using TA = float; };
+template <> struct PrecT<P_ACC64> { using TU = double; using TD = float; using T = float; using TA = double; };
+
+// Ghost cells as index maps: periodic wraps, transmissive clamps to the
+// nearest interior cell (every unknown of a ghost cell is that cell's).
+__device__ __forceinline__ int bc_map(int i, int n, int bc) {
+    if (bc == BC_PERIODIC) {
+        int r = i % n;
+        return r < 0 ? r + n : r;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ double as_double(uint64_t b) { return __longlong_as_double((long long)b); }
+
+// Lane l receives the value of lane l-1 (lane 0 keeps its own).
+template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
+// Lane l receives the value of lane l+1 (lane 63 keeps its own).
+template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
+
+// ------------------------------------------------------- physical fluxes ---
+//
+// For a state U and a derivative direction V of one side of an interface,
+// side() returns F(U) and the Jacobian-vector products (dF/dU) V and
+// (dF/dU) W: the fluxes of the differentiated system h = f'(u) v (Sec. 2.1)
+// and f^v, f^w / g^v, g^w (eq. 2D-uvw-cartesian).  DIR 0 = x, 1 = y.
+
+template <class T, int FLUX, int K, int DIR> struct Flux;
+
+template <class T, int DIR> struct Flux<T, F_ADV, 1, DIR> {
+    T a;
+    __device__ Flux(const Scheme& s) : a((T)s.adv[DIR]) {}
+    __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
+                                         T* fw) const {
+        f[0] = a * U[0];
+        fv[0] = a * V[0];
+        if (W) fw[0] = a * W[0];
+    }
+};
+
+template <class T, int DIR> struct Flux<T, F_BURGERS, 1, DIR> {
+    __device__ Flux(const Scheme&) {}
+    __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
+                                         T* fw) const {
+        f[0] = (T)0.5 * U[0] * U[0];
+        fv[0] = U[0] * V[0];
+        if (W) fw[0] = U[0] * W[0];
+    }
+};
+
+// 1D Euler, U = (rho, rho*mu, E).
+template <class T> struct Flux<T, F_EULER, 3, 0> {
+    T gm1;
+    __device__ Flux(const Scheme& s) : gm1((T)(s.gas_gamma - 1.0)) {}
+    __device__ __forceinline__ void side(const T* U, const T* V, const T*, T* f, T* fv,
+                                         T*) const {
+        const T rho = U[0], m = U[1], E = U[2];
+        const T u = m / rho;
+        const T half_u2 = (T)0.5 * u * u;
+        const T p = gm1 * (E - rho * half_u2);
+        const T Ep = E + p;
+        const T H = Ep / rho;
+        f[0] = m;
+        f[1] = m * u + p;
+        f[2] = u * Ep;
+        const T dr = V[0], dm = V[1], dE = V[2];
+        const T dp = gm1 * (dE - u * dm + half_u2 * dr);
+        fv[0] = dm;
+        fv[1] = (T)2 * u * dm - (T)2 * half_u2 * dr + dp;
+        fv[2] = H * dm + u * (dE + dp) - u * H * dr;
+    }
+};
+
+// 2D Euler, U = (rho, rho*mu, rho*nu, E); DIR selects F (x) or G (y).
+template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
+    T gm1;
+    __device__ Flux(const Scheme& s) : gm1((T)(s.gas_gamma - 1.0)) {}
+    __device__ __forceinline__ void jvp(T u, T v, T q2h, T H, const T* D, T* out) const {
+        const T dr = D[0], dm = D[1], dn = D[2], dE = D[3];
+        const T dp = gm1 * (dE - u * dm - v * dn + q2h * dr);
+        if (DIR == 0) {
+            out[0] = dm;
+            out[1] = (T)2 * u * dm - u * u * dr + dp;
+            out[2] = v * dm + u * dn - u * v * dr;
+            out[3] = H * dm + u * (dE + dp) - u * H * dr;
+        } else {
+            out[0] = dn;
+            out[1] = v * dm + u * dn - u * v * dr;
+            out[2] = (T)2 * v * dn - v * v * dr + dp;
+            out[3] = H * dn + v * (dE + dp) - v * H * dr;
+        }
+    }
+    __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
+                                         T* fw) const {
+        const T rho = U[0], m = U[1], n = U[2], E = U[3];
+        const T ir = (T)1 / rho;
+        const T u = m * ir, v = n * ir;
+        const T q2h = (T)0.5 * (u * u + v * v);
+        const T p = gm1 * (E - rho * q2h);
+        const T Ep = E + p;
+        const T H = Ep * ir;
+        if (DIR == 0) {
+            f[0] = m; f[1] = m * u + p; f[2] = m * v; f[3] = u * Ep;
+        } else {
+            f[0] = n; f[1] = n * u; f[2] = n * v + p; f[3] = v * Ep;
+        }
+        jvp(u, v, q2h, H, V, fv);
+        jvp(u, v, q2h, H, W, fw);
+    }
+};
+
+// ----------------------------------------------------- nonlinear weights ---
+//
+// omega~_m = gamma_m (1 + tau^2 / D_m), omega = omega~ / sum (eq.
+// nonlinear-weights, eq. nonlinear-weights-2D), with D_m = beta_m + eps or
+// beta_m^2 + eps, tau = mean_m |beta_0 - beta_m|.
+template <class T, int M>
+__device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s, int squared,
+                                                  T* omega) {
+    if (s.weights == W_LINEAR) {
+#pragma unroll
+        for (int m = 0; m <= M; ++m) omega[m] = (T)s.gam[m];
+        return;
+    }
+    T tau = 0;
+#pragma unroll
+    for (int m = 1; m <= M; ++m) tau += fabs(beta[0] - beta[m]);
+    tau *= (T)(1.0 / M);
+    const T tau2 = tau * tau;
+    const T eps = (T)s.eps;
+    T wt[M + 1], sum = 0;
+#pragma unroll
+    for (int m = 0; m <= M; ++m) {
+        const T den = squared ? beta[m] * beta[m] + eps : beta[m] + eps;
+        wt[m] = (T)s.gam[m] * ((T)1 + tau2 / den);
+        sum += wt[m];
+    }
+    const T inv = (T)1 / sum;
+#pragma unroll
+    for (int m = 0; m <= M; ++m) omega[m] = wt[m] * inv;
+}
+
+}  // namespace hweno

@@ -1,0 +1,161 @@
+// Fused 1D HWENO stage kernel: reconstruction (Sec. 2.1 Steps 1-3,
+// Appendix A), interface values, global Lax-Friedrichs fluxes for f and h,
+// the residual of eq. semi-discrete-scheme and the SSP-RK3 stage with the
+// modified derivative (Sec. 2.1 Step 4).
+//
+// A workgroup of 256 threads owns 254 consecutive output cells of one
+// problem: it stages the 258 averages and derivative means it needs in LDS
+// (coalesced, ghost cells through the boundary index map), reconstructs 256
+// cells (one per thread, every component), computes the 255 interface
+// fluxes once each, and updates the 254 interior cells.
+#pragma once
+
+#include "device_common.h"
+
+namespace hweno {
+
+template <int P, int K, int FLUX>
+__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
+    using TU = typename PrecT<P>::TU;
+    using TD = typename PrecT<P>::TD;
+    using T = typename PrecT<P>::T;
+    using TA = typename PrecT<P>::TA;
+    constexpr int NL = TILE1D_OUT + 4;   // staged cells
+    __shared__ TU su[K][NL];
+    __shared__ TD sv[K][NL];
+    __shared__ T sR[2 * K][256];         // (u, u_x) at x_{i+1/2} from cell i
+    __shared__ T sL[2 * K][256];         // (u, u_x) at x_{i-1/2} from cell i
+    __shared__ T sF[2 * K][256];         // (f-hat, h-hat) at the right interface of cell t
+
+    const int tid = threadIdx.x;
+    const Scheme& sch = a.sch;
+    const int squared = sch.weights == W_BETA2;   // W_PAPER prints beta + eps in 1D
+    const Flux<T, FLUX, K, 0> F(sch);
+    const Tile1D* tiles = (const Tile1D*)a.tiles + a.tile_offset;
+    const T g0inv = (T)(1.0 / sch.gam[0]);
+
+    for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
+        const Tile1D tile = tiles[tix];
+        const ProbDev& P_ = a.probs[tile.prob];
+        if (mode != MODE_RHS && !P_.active) continue;
+        const int nx = P_.nx, bcx = P_.bc_x;
+        const T dx = (T)P_.dx, inv_dx = (T)P_.inv_dx;
+        const TA inv_dx_a = (TA)P_.inv_dx;
+        const T alpha = (T)as_double(P_.ax_bits);
+        const double dt = P_.dt;
+        const int c0 = tile.c0;
+
+        for (int k = tid; k < NL; k += 256) {
+            const int src = bc_map(c0 - 2 + k, nx, bcx);
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                su[c][k] = ((const TU*)a.in.u)[P_.off_u + (int64_t)c * nx + src];
+                sv[c][k] = ((const TD*)a.in.d)[P_.off_d + (int64_t)c * nx + src];
+            }
+        }
+        __syncthreads();
+
+        // ---- reconstruct local cell tid (global c0 - 1 + tid) ---------------
+        T vhat[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const TU uc = su[c][tid + 1];
+            const T dm = (T)(su[c][tid] - uc);        // u_{i-1} - u_i
+            const T dp = (T)(su[c][tid + 2] - uc);    // u_{i+1} - u_i
+            const T dvm = dx * (T)sv[c][tid];         // dx * v_{i-1}
+            const T dvp = dx * (T)sv[c][tid + 2];     // dx * v_{i+1}
+            // Appendix A with the centre average subtracted (constant relative)
+            T c0v[5];
+            c0v[0] = (T)(-47.0 / 480.0) * (dm + dp) + (T)(9.0 / 320.0) * (dvp - dvm);
+            c0v[1] = (T)(13.0 / 16.0) * (dp - dm) - (T)(5.0 / 16.0) * (dvm + dvp);
+            c0v[2] = (T)(5.0 / 4.0) * (dm + dp) + (T)(3.0 / 8.0) * (dvm - dvp);
+            c0v[3] = (T)0.25 * (dm - dp) + (T)0.25 * (dvm + dvp);
+            c0v[4] = (T)-0.5 * (dm + dp) + (T)0.25 * (dvp - dvm);
+            T beta[3];
+            beta[0] = c0v[1] * c0v[1] + (T)4 * c0v[2] * c0v[2] + (T)36 * c0v[3] * c0v[3] +
+                      (T)576 * c0v[4] * c0v[4];
+            beta[1] = dm * dm;
+            beta[2] = dp * dp;
+            T w[3];
+            nonlinear_weights<T, 2>(beta, sch, squared, w);
+            const T a0 = w[0] * g0inv;
+            const T b1 = w[1] - a0 * (T)sch.gam[1], b2 = w[2] - a0 * (T)sch.gam[2];
+            T C[5];
+#pragma unroll
+            for (int l = 0; l < 5; ++l) C[l] = a0 * c0v[l];
+            C[1] += b2 * dp - b1 * dm;   // slopes of p1 (-dm) and p2 (dp)
+            const T E = C[0] + (T)0.25 * C[2] + (T)0.0625 * C[4];
+            const T O = (T)0.5 * C[1] + (T)0.125 * C[3];
+            const T De = C[1] + (T)0.75 * C[3], Do = C[2] + (T)0.5 * C[4];
+            const T ucT = (T)uc;
+            sR[c][tid] = ucT + (E + O);
+            sL[c][tid] = ucT + (E - O);
+            sR[K + c][tid] = (De + Do) * inv_dx;
+            sL[K + c][tid] = (De - Do) * inv_dx;
+            vhat[c] = (T)2 * O * inv_dx;   // (u(x+1/2) - u(x-1/2)) / dx
+        }
+        __syncthreads();
+
+        // ---- flux at the interface between local cells tid and tid+1 -------
+        if (tid < 255) {
+            T UL[K], VL[K], UR[K], VR[K], fL[K], hL[K], fR[K], hR[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                UL[c] = sR[c][tid]; VL[c] = sR[K + c][tid];
+                UR[c] = sL[c][tid + 1]; VR[c] = sL[K + c][tid + 1];
+            }
+            F.side(UL, VL, nullptr, fL, hL, nullptr);
+            F.side(UR, VR, nullptr, fR, hR, nullptr);
+            const T ha = (T)0.5 * alpha;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                sF[c][tid] = (T)0.5 * (fL[c] + fR[c]) - ha * (UR[c] - UL[c]);
+                sF[K + c][tid] = (T)0.5 * (hL[c] + hR[c]) - ha * (VR[c] - VL[c]);
+            }
+        }
+        __syncthreads();
+
+        // ---- residual and RK stage of local cell tid -----------------------
+        const int gi = c0 - 1 + tid;
+        if (tid >= 1 && tid <= TILE1D_OUT && gi < nx) {
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                const TA Lu = -((TA)sF[c][tid] - (TA)sF[c][tid - 1]) * inv_dx_a;
+                const T Lv = -(sF[K + c][tid] - sF[K + c][tid - 1]) * inv_dx;
+                const TA ucur = (TA)su[c][tid + 1];
+                const int64_t ou = P_.off_u + (int64_t)c * nx + gi;
+                const int64_t od = P_.off_d + (int64_t)c * nx + gi;
+                if (mode == MODE_RHS) {
+                    const int64_t ob = (int64_t)c * nx + gi;
+                    a.L_out[ob] = (double)Lu;
+                    a.L_out[(int64_t)K * nx + ob] = (double)Lv;
+                    a.Uh_out[ob] = (double)ucur;
+                    a.Uh_out[(int64_t)K * nx + ob] = (double)vhat[c];
+                } else {
+                    TU* Ou = (TU*)a.out.u;
+                    TD* Ov = (TD*)a.out.d;
+                    const TA dta = (TA)dt;
+                    const T dtt = (T)dt;
+                    if (mode == MODE_S1) {
+                        Ou[ou] = (TU)(ucur + dta * Lu);
+                        Ov[od] = (TD)(vhat[c] + dtt * Lv);
+                        ((TD*)a.h)[od] = (TD)vhat[c];
+                    } else {
+                        const TA unr = (TA)((const TU*)a.un)[ou];
+                        const T hn = (T)((const TD*)a.h)[od];
+                        if (mode == MODE_S2) {
+                            Ou[ou] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
+                            Ov[od] = (TD)((T)0.75 * hn + (T)0.25 * (vhat[c] + dtt * Lv));
+                        } else {
+                            Ou[ou] = (TU)((TA)(1.0 / 3.0) * unr + (TA)(2.0 / 3.0) * (ucur + dta * Lu));
+                            Ov[od] = (TD)((T)(1.0 / 3.0) * hn + (T)(2.0 / 3.0) * (vhat[c] + dtt * Lv));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();   // LDS reuse by the next tile
+    }
+}
+
+}  // namespace hweno

@@ -1,0 +1,420 @@
+// Fused 2D HWENO stage kernel: reconstruction (Sec. 2.2 Steps 1-3,
+// Appendix A), Gauss-point edge values, global Lax-Friedrichs edge fluxes,
+// the residual of eq. 2D-semi-discrete-scheme-uniform and the SSP-RK3 stage
+// combination with the modified derivatives (Sec. 2.2 Step 4), in one pass.
+//
+// Work decomposition ("column march"): a workgroup owns a strip of 64
+// consecutive columns (60 output columns plus two halo columns per side) and
+// marches up through a segment of rows.  Wave c handles conserved component
+// c, one column per lane, so the x-neighbours of the stencil come from the
+// adjacent lanes and the rows below/above stay in registers as the march
+// advances.  Per row:
+//   R  each (lane, component) reconstructs its cell and writes the values of
+//      U, u_x, u_y at the Gauss points of its four faces to LDS;
+//   F  each thread computes the Lax-Friedrichs flux (all components) at one
+//      edge Gauss point: the x-edges of this row and the y-edges between this
+//      row and the one below;
+//   S  each (lane, component) differences the fluxes of the row below, which
+//      now has all four edges, and applies the RK stage to it.
+// Every edge flux is computed once per workgroup and used by both cells, so
+// the update is conservative to the rounding of the cell-average arithmetic.
+#pragma once
+
+#include "device_common.h"
+
+namespace hweno {
+
+// Gauss-Legendre nodes on [-1/2, 1/2] (ascending) and weights summing to one.
+template <int Q> struct Gauss;
+template <> struct Gauss<2> {
+    static constexpr double g = 0.28867513459481288225;  // 1 / (2 sqrt 3)
+    __device__ static constexpr double w(int) { return 0.5; }
+};
+template <> struct Gauss<3> {
+    static constexpr double g = 0.38729833462074168852;  // sqrt(15) / 10
+    __device__ static constexpr double w(int mu) { return mu == 1 ? 8.0 / 18.0 : 5.0 / 18.0; }
+};
+
+// Appendix A coefficients c_{0,1..15} (stored 0..14) of the quartic p0 in
+// terms of q_1..q_17, written with the centre average subtracted from the
+// nine averages (q_5 = 0): every coefficient but the constant is invariant
+// under that shift, and the constant becomes relative to the centre.
+template <class T>
+__device__ __forceinline__ void appendix_a(const T* q, T* c) {
+    // q[0..16] hold q_1..q_17
+    const T q1 = q[0], q2 = q[1], q3 = q[2], q4 = q[3], q6 = q[5], q7 = q[6], q8 = q[7],
+            q9 = q[8];
+    const T corner = (q1 + q3) + (q7 + q9);
+    const T xdc = (q3 + q9) - (q1 + q7);
+    const T ydc = (q7 + q9) - (q1 + q3);
+    const T xyc = (q1 - q3) - (q7 - q9);
+    const T sx = q4 + q6, dxs = q6 - q4;
+    const T sy = q2 + q8, dys = q8 - q2;
+    const T vWEs = q[9] + q[10], vWEd = q[10] - q[9];
+    const T vSNs = q[11] + q[12], vSNd = q[12] - q[11];
+    const T wWEs = q[13] + q[14], wWEd = q[14] - q[13];
+    const T wSNs = q[15] + q[16], wSNd = q[16] - q[15];
+    c[0] = ((T)5 * corner - (T)292 * (sx + sy) + (T)81 * (vWEd + wSNd)) * (T)(1.0 / 2880.0);
+    c[1] = ((T)19 * dxs - (T)2 * xdc - (T)6 * vWEs + (T)3 * vSNs) * (T)(1.0 / 24.0);
+    c[2] = ((T)19 * dys - (T)2 * ydc + (T)3 * wWEs - (T)6 * wSNs) * (T)(1.0 / 24.0);
+    c[3] = ((T)62 * sx + (T)2 * sy - corner - (T)18 * vWEd) * (T)(1.0 / 48.0);
+    c[4] = ((T)5 * (vSNd + wWEd) - (T)3 * xyc) * (T)0.125;
+    c[5] = ((T)62 * sy + (T)2 * sx - corner - (T)18 * wSNd) * (T)(1.0 / 48.0);
+    c[6] = (xdc - (T)4 * dxs + (T)4 * vWEs - (T)2 * vSNs) * (T)0.05;
+    c[7] = (ydc - (T)2 * dys) * (T)0.25;
+    c[8] = (xdc - (T)2 * dxs) * (T)0.25;
+    c[9] = (ydc - (T)4 * dys - (T)2 * wWEs + (T)4 * wSNs) * (T)0.05;
+    c[10] = (vWEd - (T)2 * sx) * (T)0.25;
+    c[11] = (xyc - (T)2 * vSNd) * (T)0.25;
+    c[12] = (corner - (T)2 * (sx + sy)) * (T)0.25;
+    c[13] = (xyc - (T)2 * wWEd) * (T)0.25;
+    c[14] = (wSNd - (T)2 * sy) * (T)0.25;
+}
+
+// HWENO polynomial of one cell and component (Steps 1-3).  q: stencil with
+// the centre average subtracted.  C: coefficients of u_ij - u-bar_ij in the
+// basis 1, xi, eta, xi^2, xi eta, eta^2, xi^3, xi^2 eta, xi eta^2, eta^3,
+// xi^4, xi^3 eta, xi^2 eta^2, xi eta^3, eta^4.
+template <class T>
+__device__ __forceinline__ void reconstruct2d(const T* q, const Scheme& s, int squared, T* C,
+                                              T& vhat, T& what) {
+    T c0[15];
+    appendix_a(q, c0);
+    // linear polynomials on the L-shaped stencils S1..S4: slopes only
+    const T sW = -q[3], sE = q[5], sS = -q[1], sN = q[7];
+    // smoothness indicators: sum over monomials of (m! n! c_mn)^2
+    T b0 = c0[1] * c0[1] + c0[2] * c0[2] + c0[4] * c0[4];
+    b0 += (T)4 * (c0[3] * c0[3] + c0[5] * c0[5] + c0[7] * c0[7] + c0[8] * c0[8]);
+    b0 += (T)16 * c0[12] * c0[12];
+    b0 += (T)36 * (c0[6] * c0[6] + c0[9] * c0[9] + c0[11] * c0[11] + c0[13] * c0[13]);
+    b0 += (T)576 * (c0[10] * c0[10] + c0[14] * c0[14]);
+    T beta[5];
+    beta[0] = b0;
+    const T sW2 = sW * sW, sE2 = sE * sE, sS2 = sS * sS, sN2 = sN * sN;
+    beta[1] = sW2 + sS2;
+    beta[2] = sE2 + sS2;
+    beta[3] = sE2 + sN2;
+    beta[4] = sW2 + sN2;
+    T w[5];
+    nonlinear_weights<T, 4>(beta, s, squared, w);
+    // u_ij = w0/g0 p0 + sum_m (w_m - w0 g_m/g0) p_m   (eq. hweno-reconstruction-2D)
+    const T a0 = w[0] * (T)(1.0 / s.gam[0]);
+    T bm[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) bm[m] = w[m + 1] - a0 * (T)s.gam[m + 1];
+#pragma unroll
+    for (int l = 0; l < 15; ++l) C[l] = a0 * c0[l];
+    C[1] += sW * (bm[0] + bm[3]) + sE * (bm[1] + bm[2]);
+    C[2] += sS * (bm[0] + bm[1]) + sN * (bm[2] + bm[3]);
+    // modified derivatives: integrals of u_x, u_y over the cell (scaled units)
+    vhat = C[1] + (T)0.25 * C[6] + (T)(1.0 / 12.0) * C[8];
+    what = C[2] + (T)0.25 * C[9] + (T)(1.0 / 12.0) * C[7];
+}
+
+// Values at the Gauss points of the two faces normal to the first variable
+// of C (xi for x-faces; pass the transposed coefficients for y-faces).
+// Outputs per side s (0: -1/2, 1: +1/2) and node mu: value, derivative
+// normal to the face, derivative along the face (local units, relative
+// value).
+template <class T, int Q>
+__device__ __forceinline__ void face_values(const T* C, T (*val)[Q], T (*dn)[Q], T (*dt)[Q]) {
+    const T E0 = C[0] + (T)0.25 * C[3] + (T)0.0625 * C[10], O0 = (T)0.5 * C[1] + (T)0.125 * C[6];
+    const T E1 = C[2] + (T)0.25 * C[7], O1 = (T)0.5 * C[4] + (T)0.125 * C[11];
+    const T E2 = C[5] + (T)0.25 * C[12], O2 = (T)0.5 * C[8];
+    const T E3 = C[9], O3 = (T)0.5 * C[13];
+    const T E4 = C[14];
+    const T Eb0 = C[1] + (T)0.75 * C[6], Ob0 = C[3] + (T)0.5 * C[10];
+    const T Eb1 = C[4] + (T)0.75 * C[11], Ob1 = C[7];
+    const T Eb2 = C[8], Ob2 = C[12];
+    const T Eb3 = C[13];
+    const T g = (T)Gauss<Q>::g, g2 = g * g, g3 = g2 * g, g4 = g2 * g2;
+    // symmetric pair of nodes +-g
+    const T uee = E0 + g2 * E2 + g4 * E4, uoe = O0 + g2 * O2;
+    const T ueo = g * E1 + g3 * E3, uoo = g * O1 + g3 * O3;
+    const T nee = Eb0 + g2 * Eb2, noe = Ob0 + g2 * Ob2;
+    const T neo = g * Eb1 + g3 * Eb3, noo = g * Ob1;
+    const T tee = E1 + (T)3 * g2 * E3, toe = O1 + (T)3 * g2 * O3;
+    const T teo = (T)2 * g * E2 + (T)4 * g3 * E4, too = (T)2 * g * O2;
+    constexpr int lo = 0, hi = Q - 1;  // nodes -g and +g
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const T sg = s ? (T)1 : (T)-1;
+        const T ue = uee + sg * uoe, uo = ueo + sg * uoo;
+        const T ne = nee + sg * noe, no = neo + sg * noo;
+        const T te = tee + sg * toe, to = teo + sg * too;
+        val[s][lo] = ue - uo; val[s][hi] = ue + uo;
+        dn[s][lo] = ne - no;  dn[s][hi] = ne + no;
+        dt[s][lo] = te - to;  dt[s][hi] = te + to;
+        if (Q == 3) {
+            val[s][1] = E0 + sg * O0;
+            dn[s][1] = Eb0 + sg * Ob0;
+            dt[s][1] = E1 + sg * O1;
+        }
+    }
+}
+
+template <class T> __device__ __forceinline__ void transpose15(const T* C, T* D) {
+    D[0] = C[0]; D[1] = C[2]; D[2] = C[1]; D[3] = C[5]; D[4] = C[4]; D[5] = C[3];
+    D[6] = C[9]; D[7] = C[8]; D[8] = C[7]; D[9] = C[6]; D[10] = C[14]; D[11] = C[13];
+    D[12] = C[12]; D[13] = C[11]; D[14] = C[10];
+}
+
+// Lax-Friedrichs flux at one edge point, all components: out = (f, f^v, f^w).
+template <class T, int FLUX, int K, int DIR>
+__device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T* UL, const T* VL,
+                                        const T* WL, const T* UR, const T* VR, const T* WR,
+                                        T alpha, T* out) {
+    T fL[K], fvL[K], fwL[K], fR[K], fvR[K], fwR[K];
+    F.side(UL, VL, WL, fL, fvL, fwL);
+    F.side(UR, VR, WR, fR, fvR, fwR);
+    const T ha = (T)0.5 * alpha;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        out[c] = (T)0.5 * (fL[c] + fR[c]) - ha * (UR[c] - UL[c]);
+        out[K + c] = (T)0.5 * (fvL[c] + fvR[c]) - ha * (VR[c] - VL[c]);
+        out[2 * K + c] = (T)0.5 * (fwL[c] + fwR[c]) - ha * (WR[c] - WL[c]);
+    }
+}
+
+template <int P, int K, int Q, int FLUX>
+__global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) {
+    using TU = typename PrecT<P>::TU;
+    using TD = typename PrecT<P>::TD;
+    using T = typename PrecT<P>::T;
+    using TA = typename PrecT<P>::TA;
+    constexpr int NF = Q * 3 * K;  // face values per lane and face (all components)
+    __shared__ T sxR[NF][64], sxL[NF][64], syB[NF][64], syT[NF][64];
+    __shared__ T sFX[Q][3 * K][64], sFY[Q][3 * K][64];
+
+    const int lane = threadIdx.x & 63;
+    const int c = threadIdx.x >> 6;  // component of this wave
+    const Scheme& sch = a.sch;
+    const int squared = sch.weights == W_BETA2 || (sch.weights == W_PAPER);
+    const Flux<T, FLUX, K, 0> FXf(sch);
+    const Flux<T, FLUX, K, 1> FYf(sch);
+    const Tile2D* tiles = (const Tile2D*)a.tiles + a.tile_offset;
+
+    for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
+        const Tile2D tile = tiles[tix];
+        const ProbDev& P_ = a.probs[tile.prob];
+        if (mode != MODE_RHS && !P_.active) continue;
+        const int nx = P_.nx, ny = P_.ny, bcx = P_.bc_x, bcy = P_.bc_y;
+        const int64_t plane = (int64_t)nx * ny;
+        const T inv_dx = (T)P_.inv_dx, inv_dy = (T)P_.inv_dy;
+        const TA inv_dx_a = (TA)P_.inv_dx, inv_dy_a = (TA)P_.inv_dy;
+        const T rx = (T)(P_.dx * P_.inv_dy), ry = (T)(P_.dy * P_.inv_dx);
+        const T ax = (T)as_double(P_.ax_bits), ay = (T)as_double(P_.ay_bits);
+        const double dt = P_.dt;
+        const int gi = tile.i0 - 2 + lane;          // this lane's column
+        const int li = bc_map(gi, nx, bcx);         // column it reads
+        const bool out_col = lane >= 2 && lane < 62 && gi < nx;
+
+        const TU* Uu = (const TU*)a.in.u + P_.off_u + c * plane;
+        const TD* Uv = (const TD*)a.in.d + P_.off_d + c * plane;
+        const TD* Uw = (const TD*)a.in.d + P_.off_d + (K + c) * plane;
+
+        auto row_ptr = [&](int j) { return (int64_t)bc_map(j, ny, bcy) * nx + li; };
+        const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
+
+        TU um, u0, up, un_;
+        TD vm, v0, vp, vn_, wm, w0, wp, wn_;
+        {
+            int64_t o = row_ptr(j0 - 2);
+            um = Uu[o]; vm = Uv[o]; wm = Uw[o];
+            o = row_ptr(j0 - 1);
+            u0 = Uu[o]; v0 = Uv[o]; w0 = Uw[o];
+            o = row_ptr(j0);
+            up = Uu[o]; vp = Uv[o]; wp = Uw[o];
+        }
+        T ytop[Q][3];            // top-face values of the previous row (this lane, comp)
+        TA xd_prev[3] = {0, 0, 0};
+        TA gy_prev[3] = {0, 0, 0};
+        T hat_prev[2] = {0, 0};
+
+        for (int r = j0 - 1; r <= jend; ++r) {
+            // prefetch the row two above and the RK inputs of the output row
+            {
+                const int64_t o = row_ptr(r + 2);
+                un_ = Uu[o]; vn_ = Uv[o]; wn_ = Uw[o];
+            }
+            TA unr = 0;
+            T hvr = 0, hwr = 0;
+            const bool emit = r > j0 && out_col;   // row r-1 is an output row
+            const int64_t oo = (int64_t)(r - 1) * nx + gi;  // output row r-1 (in range if emit)
+            if (emit && (mode == MODE_S2 || mode == MODE_S3)) {
+                unr = (TA)((const TU*)a.un)[P_.off_u + c * plane + oo];
+                hvr = (T)((const TD*)a.h)[P_.off_d + c * plane + oo];
+                hwr = (T)((const TD*)a.h)[P_.off_d + (K + c) * plane + oo];
+            }
+
+            // ---- R: reconstruct cell (gi, r), component c -------------------
+            if (r > j0 - 1) {
+#pragma unroll
+                for (int mu = 0; mu < Q; ++mu)
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) syT[(mu * 3 + v) * K + c][lane] = ytop[mu][v];
+            }
+            T q[17];
+            {
+                const TU uc = u0;
+                q[0] = (T)(from_left(um) - uc);
+                q[1] = (T)(um - uc);
+                q[2] = (T)(from_right(um) - uc);
+                q[3] = (T)(from_left(u0) - uc);
+                q[4] = (T)0;
+                q[5] = (T)(from_right(u0) - uc);
+                q[6] = (T)(from_left(up) - uc);
+                q[7] = (T)(up - uc);
+                q[8] = (T)(from_right(up) - uc);
+                q[9] = (T)from_left(v0);
+                q[10] = (T)from_right(v0);
+                q[11] = (T)vm;
+                q[12] = (T)vp;
+                q[13] = (T)from_left(w0);
+                q[14] = (T)from_right(w0);
+                q[15] = (T)wm;
+                q[16] = (T)wp;
+            }
+            T C[15], vhat, what;
+            reconstruct2d<T>(q, sch, squared, C, vhat, what);
+            const T ucT = (T)u0;
+            {
+                T val[2][Q], dn[2][Q], dtg[2][Q];
+                face_values<T, Q>(C, val, dn, dtg);   // x-faces: dn = d/dxi, dt = d/deta
+#pragma unroll
+                for (int mu = 0; mu < Q; ++mu) {
+                    sxL[(mu * 3 + 0) * K + c][lane] = ucT + val[0][mu];
+                    sxL[(mu * 3 + 1) * K + c][lane] = dn[0][mu] * inv_dx;
+                    sxL[(mu * 3 + 2) * K + c][lane] = dtg[0][mu] * inv_dy;
+                    sxR[(mu * 3 + 0) * K + c][lane] = ucT + val[1][mu];
+                    sxR[(mu * 3 + 1) * K + c][lane] = dn[1][mu] * inv_dx;
+                    sxR[(mu * 3 + 2) * K + c][lane] = dtg[1][mu] * inv_dy;
+                }
+                T D[15];
+                transpose15(C, D);
+                face_values<T, Q>(D, val, dn, dtg);   // y-faces: dn = d/deta, dt = d/dxi
+#pragma unroll
+                for (int mu = 0; mu < Q; ++mu) {
+                    syB[(mu * 3 + 0) * K + c][lane] = ucT + val[0][mu];
+                    syB[(mu * 3 + 1) * K + c][lane] = dtg[0][mu] * inv_dx;
+                    syB[(mu * 3 + 2) * K + c][lane] = dn[0][mu] * inv_dy;
+                    ytop[mu][0] = ucT + val[1][mu];
+                    ytop[mu][1] = dtg[1][mu] * inv_dx;
+                    ytop[mu][2] = dn[1][mu] * inv_dy;
+                }
+            }
+
+            if (r > j0 - 1) {
+                __syncthreads();  // A: face values of row r (and top faces of r-1) ready
+                // ---- F: edge fluxes ---------------------------------------
+                for (int sl = threadIdx.x; sl < 2 * Q * 64; sl += 64 * K) {
+                    const int kind = sl / (Q * 64);
+                    const int mu = (sl >> 6) % Q;
+                    const int l = sl & 63;
+                    T UL[K], VL[K], WL[K], UR[K], VR[K], WR[K], out[3 * K];
+                    if (kind == 0) {
+                        if (l < 63) {   // x-edge between lanes l and l+1
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                UL[k] = sxR[(mu * 3 + 0) * K + k][l];
+                                VL[k] = sxR[(mu * 3 + 1) * K + k][l];
+                                WL[k] = sxR[(mu * 3 + 2) * K + k][l];
+                                UR[k] = sxL[(mu * 3 + 0) * K + k][l + 1];
+                                VR[k] = sxL[(mu * 3 + 1) * K + k][l + 1];
+                                WR[k] = sxL[(mu * 3 + 2) * K + k][l + 1];
+                            }
+                            lf_edge<T, FLUX, K, 0>(FXf, UL, VL, WL, UR, VR, WR, ax, out);
+#pragma unroll
+                            for (int k = 0; k < 3 * K; ++k) sFX[mu][k][l] = out[k];
+                        }
+                    } else {            // y-edge between rows r-1 and r, column l
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            UL[k] = syT[(mu * 3 + 0) * K + k][l];
+                            VL[k] = syT[(mu * 3 + 1) * K + k][l];
+                            WL[k] = syT[(mu * 3 + 2) * K + k][l];
+                            UR[k] = syB[(mu * 3 + 0) * K + k][l];
+                            VR[k] = syB[(mu * 3 + 1) * K + k][l];
+                            WR[k] = syB[(mu * 3 + 2) * K + k][l];
+                        }
+                        lf_edge<T, FLUX, K, 1>(FYf, UL, VL, WL, UR, VR, WR, ay, out);
+#pragma unroll
+                        for (int k = 0; k < 3 * K; ++k) sFY[mu][k][l] = out[k];
+                    }
+                }
+                __syncthreads();  // B: fluxes ready
+                // ---- S: residual and RK stage of row r-1 ------------------
+                TA xd[3], gy[3];
+#pragma unroll
+                for (int sk = 0; sk < 3; ++sk) {
+                    T fr = 0, fl = 0, g = 0;
+#pragma unroll
+                    for (int mu = 0; mu < Q; ++mu) {
+                        const T w = (T)Gauss<Q>::w(mu);
+                        fr += w * sFX[mu][sk * K + c][lane];
+                        fl += w * sFX[mu][sk * K + c][lane > 0 ? lane - 1 : 0];
+                        g += w * sFY[mu][sk * K + c][lane];
+                    }
+                    xd[sk] = (TA)fr - (TA)fl;
+                    gy[sk] = (TA)g;
+                }
+                if (r > j0) {
+                    const TA Lu = -(xd_prev[0] * inv_dx_a + (gy[0] - gy_prev[0]) * inv_dy_a);
+                    const T Lv = -((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
+                    const T Lw = -(ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
+                    if (emit) {
+                        const TA ucur = (TA)um;   // u-bar of row r-1 in the input set
+                        if (mode == MODE_RHS) {
+                            const int64_t ob = (int64_t)c * plane + oo;
+                            a.L_out[ob] = (double)Lu;
+                            a.L_out[K * plane + ob] = (double)Lv;
+                            a.L_out[2 * K * plane + ob] = (double)Lw;
+                            a.Uh_out[ob] = (double)ucur;
+                            a.Uh_out[K * plane + ob] = (double)hat_prev[0];
+                            a.Uh_out[2 * K * plane + ob] = (double)hat_prev[1];
+                        } else {
+                            TU* Ou = (TU*)a.out.u + P_.off_u + c * plane;
+                            TD* Ov = (TD*)a.out.d + P_.off_d + c * plane;
+                            TD* Ow = (TD*)a.out.d + P_.off_d + (K + c) * plane;
+                            const TA dta = (TA)dt;
+                            const T dtt = (T)dt;
+                            if (mode == MODE_S1) {
+                                Ou[oo] = (TU)(ucur + dta * Lu);
+                                Ov[oo] = (TD)(hat_prev[0] + dtt * Lv);
+                                Ow[oo] = (TD)(hat_prev[1] + dtt * Lw);
+                                TD* H = (TD*)a.h + P_.off_d;
+                                H[c * plane + oo] = (TD)hat_prev[0];
+                                H[(K + c) * plane + oo] = (TD)hat_prev[1];
+                            } else if (mode == MODE_S2) {
+                                Ou[oo] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
+                                Ov[oo] = (TD)((T)0.75 * hvr + (T)0.25 * (hat_prev[0] + dtt * Lv));
+                                Ow[oo] = (TD)((T)0.75 * hwr + (T)0.25 * (hat_prev[1] + dtt * Lw));
+                            } else {
+                                const TA third = (TA)(1.0 / 3.0), two3 = (TA)(2.0 / 3.0);
+                                Ou[oo] = (TU)(third * unr + two3 * (ucur + dta * Lu));
+                                Ov[oo] = (TD)((T)(1.0 / 3.0) * hvr +
+                                              (T)(2.0 / 3.0) * (hat_prev[0] + dtt * Lv));
+                                Ow[oo] = (TD)((T)(1.0 / 3.0) * hwr +
+                                              (T)(2.0 / 3.0) * (hat_prev[1] + dtt * Lw));
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int sk = 0; sk < 3; ++sk) {
+                    xd_prev[sk] = xd[sk];
+                    gy_prev[sk] = gy[sk];
+                }
+            }
+            hat_prev[0] = vhat;
+            hat_prev[1] = what;
+            // advance the register window one row up
+            um = u0; u0 = up; up = un_;
+            vm = v0; v0 = vp; vp = vn_;
+            wm = w0; w0 = wp; wp = wn_;
+        }
+        __syncthreads();  // LDS reuse by the next tile
+    }
+}
+
+}  // namespace hweno
