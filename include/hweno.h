@@ -179,6 +179,21 @@ int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
  * and keeps the fastest.  Synchronising.  best (may be NULL) receives it. */
 int hweno_autotune(hweno_handle* h, hweno_tuning* best);
 
+/* Per-kernel timing of nsteps steps (CFL rule), launched eagerly on the
+ * handle's stream with a HIP event pair around every kernel.  Synchronising.
+ * total_ms: first to last event; stage_ms: sum of the fused stage kernels;
+ * alpha_ms: wave-speed reductions; other_ms: dt and time-update kernels. */
+typedef struct {
+    double total_ms;
+    double stage_ms;
+    double alpha_ms;
+    double other_ms;
+    int64_t steps;        /* steps in which some problem advanced */
+    int64_t stage_launches;
+} hweno_timing;
+
+int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* out);
+
 int hweno_destroy(hweno_handle* h);
 
 /* Text of the last error on h, or of the last failed hweno_create on this

@@ -356,7 +356,7 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     ctl.dim = h->dim;
     HIP_TRY(h, hipMemcpy(h->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));
     h->state_set.assign(nprob, 0);
-    h->tun.tile_rows = 64;
+    h->tun.tile_rows = 32;
     h->tun.grid_blocks = 0;
     h->tun.use_graph = 1;
     return build_tiles(h);
@@ -737,4 +737,65 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     if (rc) return rc;
     if (best) *best = win;
     return HWENO_OK;
+}
+
+// ---------------------------------------------------------------- timing
+
+extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* out) {
+    if (!h || !out || nsteps < 0) return HWENO_ERR_ARG;
+    int rc = all_set(h);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof *out);
+    const int per_step = 7;
+    std::vector<hipEvent_t> ev(2 * per_step * (size_t)nsteps + 2);
+    for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
+    StepCtl c0{}, c1{};
+    HIP_TRY(h, hipMemcpyAsync(&c0, h->d_ctl, sizeof c0, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    size_t k = 0;
+    HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+    const size_t first = 1;
+    for (int s = 0; s < nsteps; ++s) {
+        auto rec = [&](hipError_t launched) -> hipError_t {
+            if (launched != hipSuccess) return launched;
+            return hipEventRecord(ev[k++], h->stream);
+        };
+        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+        HIP_TRY(h, rec(launch_reset(h->d_probs, h->d_ctl, h->nprob, h->stream)));
+        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+        HIP_TRY(h, rec(launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs,
+                                    h->d_chunks, h->nchunks, h->sch, 0, 0, h->stream)));
+        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+        HIP_TRY(h, rec(launch_dt(h->d_probs, h->d_ctl, h->nprob, 0, h->stream)));
+        for (int mode = MODE_S1; mode <= MODE_S3; ++mode) {
+            HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+            HIP_TRY(h, rec(launch_stage(h, mode, stage_args(h, mode))));
+        }
+        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+        HIP_TRY(h, rec(launch_finish(h->d_probs, h->d_ctl, h->nprob, h->stream)));
+    }
+    HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
+    HIP_TRY(h, hipEventSynchronize(ev[k - 1]));
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, ev[0], ev[k - 1]));
+    out->total_ms = ms;
+    // pairs in launch order: reset, alpha, dt, stage x3, finish
+    size_t e = first;
+    for (int s = 0; s < nsteps; ++s)
+        for (int j = 0; j < per_step; ++j, e += 2) {
+            HIP_TRY(h, hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
+            if (j >= 3 && j <= 5) {
+                out->stage_ms += ms;
+                out->stage_launches += 1;
+            } else if (j == 1) {
+                out->alpha_ms += ms;
+            } else {
+                out->other_ms += ms;
+            }
+        }
+    for (auto& x : ev) hipEventDestroy(x);
+    HIP_TRY(h, hipMemcpyAsync(&c1, h->d_ctl, sizeof c1, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    out->steps = c1.steps - c0.steps;
+    return hweno_sync(h);
 }

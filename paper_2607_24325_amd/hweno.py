@@ -41,6 +41,11 @@ class hweno_tuning(C.Structure):
                 ("use_graph", C.c_int32), ("reserved", C.c_int32)]
 
 
+class hweno_timing(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("stage_ms", C.c_double), ("alpha_ms", C.c_double),
+                ("other_ms", C.c_double), ("steps", C.c_int64), ("stage_launches", C.c_int64)]
+
+
 class HwenoError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -51,7 +56,7 @@ _lib = None
 EXPORTS = ["hweno_default_config", "hweno_workspace_bytes", "hweno_create", "hweno_set_state",
            "hweno_get_state", "hweno_rhs", "hweno_alpha", "hweno_step", "hweno_run_to_time",
            "hweno_sync", "hweno_get_tuning", "hweno_set_tuning", "hweno_autotune",
-           "hweno_destroy", "hweno_last_error"]
+           "hweno_timed_steps", "hweno_destroy", "hweno_last_error"]
 
 
 def lib():
@@ -79,6 +84,7 @@ def lib():
         L.hweno_get_tuning.argtypes = [H, P(hweno_tuning)]
         L.hweno_set_tuning.argtypes = [H, P(hweno_tuning)]
         L.hweno_autotune.argtypes = [H, P(hweno_tuning)]
+        L.hweno_timed_steps.argtypes = [H, C.c_int32, P(hweno_timing)]
         L.hweno_destroy.argtypes = [H]
         L.hweno_last_error.argtypes = [H]
         L.hweno_last_error.restype = C.c_char_p
@@ -231,4 +237,9 @@ class Handle:
     def autotune(self) -> hweno_tuning:
         t = hweno_tuning()
         self._check(lib().hweno_autotune(self.h, C.byref(t)))
+        return t
+
+    def timed_steps(self, nsteps: int) -> hweno_timing:
+        t = hweno_timing()
+        self._check(lib().hweno_timed_steps(self.h, nsteps, C.byref(t)))
         return t

@@ -33,3 +33,33 @@ def l1_rel(gpu, ref):
     den = np.abs(r).mean(axis=ax)
     den = np.where(den > 0, den, 1.0)
     return float((np.abs(g - r).mean(axis=ax) / den).max())
+
+
+def natural_scales(spec, st):
+    """Scale of every (var, comp) plane of a state: max |u-bar| for averages;
+    for derivative averages the larger of their own max and the range of the
+    component's averages over one cell (range/dx in 1D, where v-bar is a
+    mean of u_x; range in 2D, where v-bar and w-bar are scaled by the cell
+    size).  Limited derivatives next to a jump are tiny in absolute terms,
+    and rounding there is measured against this scale."""
+    S = np.zeros((spec.nvar, spec.K))
+    for c in range(spec.K):
+        u = st[0, c]
+        rng = float(u.max() - u.min())
+        S[0, c] = np.abs(u).max()
+        for v in range(1, spec.nvar):
+            S[v, c] = max(np.abs(st[v, c]).max(), rng / (spec.dx if spec.dim == 1 else 1.0))
+    return np.where(S > 0, S, 1.0)
+
+
+def scaled_err(gpu, ref, scales):
+    """max over planes of max |gpu - ref| / scale of the plane"""
+    d = np.abs(np.asarray(gpu, dtype=np.float64) - np.asarray(ref, dtype=np.float64))
+    return float((d.max(axis=tuple(range(2, d.ndim))) / scales).max())
+
+
+def rhs_scales(spec, st, ax, ay):
+    """Scale of L: the state scale times the largest rate alpha_x/dx (+
+    alpha_y/dy) at which the scheme moves it."""
+    rate = ax / spec.dx + (ay / spec.dy if spec.dim == 2 else 0.0)
+    return natural_scales(spec, st) * max(rate, 1e-300)

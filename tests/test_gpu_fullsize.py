@@ -1,0 +1,81 @@
+"""GPU parity at the benchmark's full size (2D Euler 2048^2, Q = 2, CFL 0.5,
+quadrant states + vortex, seed 7), in the launch configuration bench.py
+times, on sampled cells the oracle computes one window at a time; and a
+whole run to t = 0.1 at 256^2 against the whole-grid oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import oproblem, natural_scales, scaled_err
+from paper_2607_24325_amd import hweno as hw
+from paper_2607_24325_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 2048
+
+
+def windows(n):
+    """corners, quadrant lines, the vortex region, strip (60 columns) and
+    segment (32 rows) boundaries of the tiling"""
+    return [(0, 0, 4, 4), (n - 4, n - 4, 4, 4), (n // 2 - 2, n // 2 - 2, 4, 4),
+            (58, 62, 5, 5), (n // 2 - 2, 7, 4, 4), (500, 500, 4, 4), (1 + n // 5, n - 3, 6, 3),
+            (n - 6, n // 3, 6, 4), (2038, 30, 10, 4)]
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return W.quadrant_vortex_2d(N, seed=7)
+
+
+@pytest.mark.parametrize("prec,tol", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-6), (hw.F32, 2e-6)])
+def test_fullsize_step_sampled(workload, prec, tol):
+    spec, st = workload
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dt = h.step(want_dt=True)[0]
+        out, t = h.get_state(0)
+    p = oproblem(spec, cfg)
+    O.set_threads(os.cpu_count() or 1)
+    ax, ay = O.alpha(p, st)
+    assert abs(dt - O.dt(p, ax, ay, 0.5)) <= (1e-14 if prec == hw.F64 else 1e-6) * dt
+    S = natural_scales(spec, st)
+    for (i0, j0, wi, wj) in windows(N):
+        ref = O.step_window(p, st, ax, ay, dt, i0, j0, wi, wj)
+        got = out[:, :, j0:j0 + wj, i0:i0 + wi]
+        assert scaled_err(got, ref, S) < tol, (i0, j0, scaled_err(got, ref, S))
+
+
+def test_fullsize_conservation_f32acc64(workload):
+    """Periodic totals of the cell averages after 5 steps, FP32 bulk with
+    FP64 cell averages: fixed to double rounding."""
+    spec, st = workload
+    cfg = hw.default_config(2, precision=hw.F32_ACC64, gauss_q=2, cfl=0.5)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        for _ in range(5):
+            h.step()
+        out, _ = h.get_state(0)
+    tot0 = st[0].sum(axis=(1, 2))
+    drift = np.abs(out[0].sum(axis=(1, 2)) - tot0) / np.abs(tot0)
+    assert np.all(drift < 1e-12), drift
+
+
+def test_full_run_256_to_final_time():
+    """Quadrant + vortex at 256^2 to t = 0.1 (Q = 2, CFL 0.5): same number of
+    steps, final state within 1e-10 of the oracle (FP64)."""
+    spec, st = W.quadrant_vortex_2d(256, seed=7)
+    cfg = hw.default_config(2, precision=hw.F64, gauss_q=2, cfl=0.5)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        steps = h.run_to_time()
+        out, t = h.get_state(0)
+    p = oproblem(spec, cfg)
+    O.set_threads(os.cpu_count() or 1)
+    ref, n = O.run(p, st, 0.0, 0.1, 0.5)
+    assert steps == n and t == 0.1
+    assert np.abs(out[0] - ref[0]).mean() <= 1e-10
+    assert scaled_err(out, ref, natural_scales(spec, st)) < 1e-9

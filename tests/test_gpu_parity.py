@@ -1,15 +1,16 @@
 """GPU parity: the HIP path, called through the C ABI, against the FP64 CPU
 oracle on the same seeded inputs (element by element).
 
-FP64 bar: 1e-12 relative to each plane's magnitude, per operator evaluation
-and per step (SURVEY/spec bar); results that only differ in the order
-of the IEEE operations stay far below it.
+FP64 bar: 1e-12 relative, per operator evaluation and per step, each
+(variable, component) plane measured against its natural scale (see
+gpu_util.natural_scales; L against the state scale times alpha/dx).
+Results that only differ in the order of the IEEE operations stay far below.
 """
 import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import oproblem, plane_rel, l1_rel
+from gpu_util import oproblem, plane_rel, l1_rel, natural_scales, scaled_err, rhs_scales
 from paper_2607_24325_amd import hweno as hw
 from paper_2607_24325_amd import workloads as W
 
@@ -64,9 +65,9 @@ def test_2d_rhs_f64(case, Q):
     oax, oay = O.alpha(p, st)
     assert abs(ax - oax) <= 1e-15 * oax and abs(ay - oay) <= 1e-15 * max(oay, 1e-300)
     Lr, Uhr = O.rhs(p, st, ax, ay)
-    # L carries a 1/dx of flux differences: measure against the flux scale too
-    assert plane_rel(Uh, Uhr) < F64_TOL
-    assert plane_rel(L, Lr) < 1e-11, plane_rel(L, Lr)
+    S = natural_scales(spec, st)
+    assert scaled_err(Uh, Uhr, S) < F64_TOL, scaled_err(Uh, Uhr, S)
+    assert scaled_err(L, Lr, rhs_scales(spec, st, ax, ay)) < F64_TOL
 
 
 @pytest.mark.parametrize("case", list(CASES_2D))
@@ -80,7 +81,8 @@ def test_2d_step_f64(case):
     ax, ay = O.alpha(p, st)
     assert abs(dt - O.dt(p, ax, ay, cfg.cfl)) <= 1e-14 * dt
     ref = O.step(p, st, ax, ay, dt)
-    assert plane_rel(gpu, ref) < F64_TOL, plane_rel(gpu, ref)
+    err = scaled_err(gpu, ref, natural_scales(spec, st))
+    assert err < F64_TOL, err
     assert t == dt
 
 
@@ -103,10 +105,11 @@ def test_1d_rhs_and_step_f64(case):
         gpu, _ = h.get_state(0)
     p = oproblem(spec, cfg)
     Lr, Uhr = O.rhs(p, st, ax, 0.0)
-    assert plane_rel(Uh, Uhr) < F64_TOL
-    assert plane_rel(L, Lr) < 1e-11
+    S = natural_scales(spec, st)
+    assert scaled_err(Uh, Uhr, S) < F64_TOL, scaled_err(Uh, Uhr, S)
+    assert scaled_err(L, Lr, rhs_scales(spec, st, ax, 0.0)) < F64_TOL
     ref = O.step(p, st, ax, 0.0, dt)
-    assert plane_rel(gpu, ref) < F64_TOL
+    assert scaled_err(gpu, ref, S) < F64_TOL, scaled_err(gpu, ref, S)
 
 
 def test_1d_advection_headline_run_to_time():
@@ -121,7 +124,7 @@ def test_1d_advection_headline_run_to_time():
     ref, n = O.run(p, st, 0.0, 2.0, 0.6)
     assert steps == n == 334 and t == 2.0
     assert np.abs(gpu[0] - ref[0]).mean() <= 1e-10
-    assert plane_rel(gpu, ref) < 1e-10
+    assert scaled_err(gpu, ref, natural_scales(spec, st)) < 1e-10
 
 
 # ------------------------------------------------------ reduced precision --
@@ -204,7 +207,7 @@ def test_batched_2d_uneven_problems():
         p = oproblem(spec, cfg)
         ax, ay = O.alpha(p, s)
         assert abs(dt - O.dt(p, ax, ay, cfg.cfl)) <= 1e-14 * dt
-        assert plane_rel(g, O.step(p, s, ax, ay, dt)) < F64_TOL
+        assert scaled_err(g, O.step(p, s, ax, ay, dt), natural_scales(spec, s)) < F64_TOL
 
 
 def test_batched_1d_uneven_problems_run_to_time():
@@ -223,7 +226,7 @@ def test_batched_1d_uneven_problems_run_to_time():
         ref, n = O.run(p, s, 0.0, 0.02, cfg.cfl)
         nmax = max(nmax, n)
         assert t == 0.02
-        assert plane_rel(g, ref) < 1e-10
+        assert scaled_err(g, ref, natural_scales(spec, s)) < 1e-10
     assert steps == nmax
 
 
