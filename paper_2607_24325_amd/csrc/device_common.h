@@ -29,10 +29,36 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc) {
 
 __device__ __forceinline__ double as_double(uint64_t b) { return __longlong_as_double((long long)b); }
 
-// Lane l receives the value of lane l-1 (lane 0 keeps its own).
-template <class T> __device__ __forceinline__ T from_left(T v) { return __shfl_up(v, 1, 64); }
-// Lane l receives the value of lane l+1 (lane 63 keeps its own).
-template <class T> __device__ __forceinline__ T from_right(T v) { return __shfl_down(v, 1, 64); }
+// Whole-wave lane shifts through DPP (wave_shr:1 / wave_shl:1 of the GFX9
+// data-parallel primitives): lane l receives lane l-1 (from_left) or lane l+1
+// (from_right); the lane at the end of the wave keeps its own value.
+template <int CTRL> __device__ __forceinline__ int dpp_shift(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+template <int CTRL> __device__ __forceinline__ float dpp_shift(float v) {
+    return __int_as_float(dpp_shift<CTRL>(__float_as_int(v)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shift(double v) {
+    const int lo = dpp_shift<CTRL>(__double2loint(v));
+    const int hi = dpp_shift<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <class T> __device__ __forceinline__ T from_left(T v) { return dpp_shift<DPP_WAVE_SHR1>(v); }
+template <class T> __device__ __forceinline__ T from_right(T v) { return dpp_shift<DPP_WAVE_SHL1>(v); }
+
+// Reciprocals: v_rcp_f32 (1 ulp) in single precision; in double precision
+// v_rcp_f64 refined by two Newton steps, r <- r + r (1 - x r), to within an
+// ulp or two of the correctly rounded quotient.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 
 // ------------------------------------------------------- physical fluxes ---
 //
@@ -71,11 +97,12 @@ template <class T> struct Flux<T, F_EULER, 3, 0> {
     __device__ __forceinline__ void side(const T* U, const T* V, const T*, T* f, T* fv,
                                          T*) const {
         const T rho = U[0], m = U[1], E = U[2];
-        const T u = m / rho;
+        const T ir = rcp(rho);
+        const T u = m * ir;
         const T half_u2 = (T)0.5 * u * u;
         const T p = gm1 * (E - rho * half_u2);
         const T Ep = E + p;
-        const T H = Ep / rho;
+        const T H = Ep * ir;
         f[0] = m;
         f[1] = m * u + p;
         f[2] = u * Ep;
@@ -109,7 +136,7 @@ template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
     __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
                                          T* fw) const {
         const T rho = U[0], m = U[1], n = U[2], E = U[3];
-        const T ir = (T)1 / rho;
+        const T ir = rcp(rho);
         const T u = m * ir, v = n * ir;
         const T q2h = (T)0.5 * (u * u + v * v);
         const T p = gm1 * (E - rho * q2h);
@@ -148,10 +175,10 @@ __device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
         const T den = squared ? beta[m] * beta[m] + eps : beta[m] + eps;
-        wt[m] = (T)s.gam[m] * ((T)1 + tau2 / den);
+        wt[m] = (T)s.gam[m] * ((T)1 + tau2 * rcp(den));
         sum += wt[m];
     }
-    const T inv = (T)1 / sum;
+    const T inv = rcp(sum);
 #pragma unroll
     for (int m = 0; m <= M; ++m) omega[m] = wt[m] * inv;
 }
