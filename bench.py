@@ -40,6 +40,53 @@ def algorithmic_bytes_per_cell_stage(K: int, D: int, su: int, sd: int) -> float:
     return (6 * S + 3 * H + 2 * K * su) / 3.0
 
 
+def bench_batched(dim: int, prec: int, steps: int, warmup: int, dev, profile_only=False):
+    """Throughput of one of the batched workloads: 4096 uneven 1D Euler
+    problems (N ~ U{256..8192}, seed 1) or 256 uneven 2D Euler problems
+    (side ~ U{128..1024}, seed 11, Q = 2, CFL 0.5); one launch per RK stage
+    over every problem, per-problem dt."""
+    import torch
+    from paper_2607_24325_amd import hweno as hw
+    from paper_2607_24325_amd import workloads as W
+    t0 = time.time()
+    if dim == 1:
+        entries = W.batched_1d(seed=1, nprob=4096)
+        make = W.batched_1d_state
+        cfg = hw.default_config(1, precision=prec)
+        K, su, sd = 3, 8, (8 if prec == hw.F64 else 4)
+    else:
+        entries = W.batched_2d(seed=11, nprob=256)
+        make = W.batched_2d_state
+        cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
+        K, su, sd = 4, 8, (8 if prec == hw.F64 else 4)
+    specs = [e[0] for e in entries]
+    ncell = sum(s.nx * s.ny for s in specs)
+    ws = torch.empty(hw.Handle.workspace_bytes(specs, cfg), dtype=torch.uint8, device=dev)
+    h = hw.Handle(specs, cfg, workspace=ws, stream=torch.cuda.current_stream(dev).cuda_stream)
+    for i, e in enumerate(entries):
+        h.set_state(i, make(e))
+    print(f"[bench] batched {dim}D: {len(specs)} problems, {ncell} cells, set up in "
+          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        h.step()
+    torch.cuda.synchronize()
+    tm = h.timed_steps(steps)
+    torch.cuda.synchronize()
+    assert tm.steps == steps
+    ms_step = tm.total_ms / steps
+    stage_ms = tm.stage_ms / tm.stage_launches
+    B = algorithmic_bytes_per_cell_stage(K, dim, su, sd)
+    h.close()
+    del ws
+    r = {"problems": len(specs), "cells": ncell, "value": 3.0 * ncell / (ms_step * 1e-3),
+         "unit": "cell-stage updates/s", "ms_per_step": ms_step, "stage_kernel_ms": stage_ms,
+         "bytes_per_cell_stage": B, "stage_hbm_frac": B * ncell / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+         "precision": "F32 bulk, FP64 cell averages" if prec != hw.F64 else "F64"}
+    print(f"[bench] batched {dim}D: {ms_step:.3f} ms/step, stage {stage_ms:.3f} ms, "
+          f"{r['value'] / 1e9:.2f} G cell-stage/s", file=sys.stderr, flush=True)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +98,9 @@ def main():
     ap.add_argument("--precision", default="both", choices=["both", "f32acc64", "f64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB with a plain device copy (HBM counter scale)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--only-batched", type=int, default=0, choices=[0, 1, 2],
+                    help="run only the batched 1D or 2D workload (profiling)")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the timed steps (for profilers)")
     args = ap.parse_args()
@@ -72,6 +122,10 @@ def main():
     print(f"[bench] workload built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     ncell = n * n
 
+    if args.only_batched:
+        r = bench_batched(args.only_batched, hw.F32_ACC64, args.steps, args.warmup, dev)
+        print(json.dumps({f"batched_{args.only_batched}d": r}))
+        return
     results = {}
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -149,6 +203,10 @@ def main():
                "sample": f"one full SSP-RK3 step of the {n}x{n} 2D Euler workload (FP64 oracle, "
                          f"OpenMP over rows), {el:.1f}s"}
 
+    batched = {}
+    if not args.no_batched:
+        for d in (1, 2):
+            batched[f"batched_{d}d"] = bench_batched(d, hw.F32_ACC64, args.steps, args.warmup, dev)
     B = main_r["bytes_per_cell_stage"]
     achieved = main_r["stage_hbm_gbs"]
     line = {
@@ -179,6 +237,7 @@ def main():
         "tuning": main_r.get("tuning"),
         "cpu_baseline": cpu,
     }
+    line.update(batched)
     print(json.dumps(line))
 
 

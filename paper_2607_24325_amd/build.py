@@ -19,7 +19,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
-SOURCES = ["stage2d_f64.hip", "stage2d_f32.hip", "stage2d_acc64.hip", "stage2d.hip",
+SOURCES = ["stage2d_f64.hip", "stage2d_f32.hip", "stage2d_acc64.hip", "stage2d_kahan.hip",
+           "stage2d.hip",
            "stage1d.hip", "control.hip", "api.cpp"]
 
 

@@ -79,7 +79,7 @@ static int ncomp_of(const hweno_problem& p) {
 }
 
 static void prec_sizes(int prec, size_t* su, size_t* sd) {
-    *su = (prec == HWENO_F64 || prec == HWENO_F32_ACC64) ? 8 : 4;
+    *su = prec == HWENO_F32 ? 4 : 8;   // F32_KAHAN keeps (hi, lo) float pairs
     *sd = prec == HWENO_F64 ? 8 : 4;
 }
 
@@ -121,7 +121,7 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
             q.adv[1] != probs[0].adv[1])
             return fail(h, HWENO_ERR_ARG, "problem %d: gas_gamma/adv differ from problem 0", p);
     }
-    if (cfg->precision < HWENO_F64 || cfg->precision > HWENO_F32_ACC64)
+    if (cfg->precision < HWENO_F64 || cfg->precision > HWENO_F32_KAHAN)
         return fail(h, HWENO_ERR_ARG, "precision %d not supported", cfg->precision);
     if (dim == 2 && cfg->gauss_q != 2 && cfg->gauss_q != 3)
         return fail(h, HWENO_ERR_ARG, "gauss_q must be 2 or 3");
@@ -437,15 +437,14 @@ extern "C" int hweno_set_state(hweno_handle* h, int32_t prob, const double* src,
                               h->stream));
     HIP_TRY(h, launch_pack(h->prec, 1, h->d_stage, h->U[0], h->h_probs[prob].off_u,
                            h->h_probs[prob].off_d, h->K, h->nvar, h->ncell[prob], h->stream));
-    std::vector<ProbDev> v;
-    rc = read_probs(h, v);
-    if (rc) return rc;
-    v[prob].t = t;
-    v[prob].err = 0;
-    v[prob].bad_cell = INT64_MAX;
-    v[prob].active = 0;
-    HIP_TRY(h, hipMemcpyAsync(h->d_probs + prob, &v[prob], sizeof(ProbDev),
-                              hipMemcpyHostToDevice, h->stream));
+    ProbDev d;
+    HIP_TRY(h, hipMemcpyAsync(&d, h->d_probs + prob, sizeof d, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    d.t = t;
+    d.err = 0;
+    d.bad_cell = INT64_MAX;
+    d.active = 0;
+    HIP_TRY(h, hipMemcpyAsync(h->d_probs + prob, &d, sizeof d, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->state_set[prob] = 1;
     return HWENO_OK;
@@ -457,9 +456,10 @@ extern "C" int hweno_get_state(hweno_handle* h, int32_t prob, double* dst,
     if (rc) return rc;
     if (!h->state_set[prob]) return fail(h, HWENO_ERR_STATE, "problem %d has no state yet", prob);
     const int64_t n = (int64_t)h->nvar * h->K * h->ncell[prob];
-    std::vector<ProbDev> v;
-    rc = read_probs(h, v);
-    if (rc) return rc;
+    std::vector<ProbDev> v(h->nprob);
+    HIP_TRY(h, hipMemcpyAsync(&v[prob], h->d_probs + prob, sizeof(ProbDev), hipMemcpyDeviceToHost,
+                              h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     if (dst) {
         HIP_TRY(h, launch_pack(h->prec, 0, h->d_stage, h->U[0], h->h_probs[prob].off_u,
                                h->h_probs[prob].off_d, h->K, h->nvar, h->ncell[prob], h->stream));

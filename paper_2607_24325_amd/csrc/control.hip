@@ -200,6 +200,7 @@ hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* pro
                         int grid, hipStream_t s) {
     if (grid <= 0 || grid > nchunks) grid = nchunks;
     if (prec == P_F32) return alpha_dispatch<P_F32>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
+    if (prec == P_KAHAN) return alpha_dispatch<P_KAHAN>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
     return alpha_dispatch<P_F64>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
 }
 
@@ -223,9 +224,12 @@ hipError_t launch_pack(int prec, int to_internal, double* ext, StateBuf buf, int
     } else if (prec == P_F32) {
         pack_kernel<float, float><<<grid, 256, 0, s>>>(to_internal, ext, (float*)buf.u + off_u,
                                                        (float*)buf.d + off_d, K, nvar, ncell);
-    } else {
+    } else if (prec == P_ACC64) {
         pack_kernel<double, float><<<grid, 256, 0, s>>>(to_internal, ext, (double*)buf.u + off_u,
                                                         (float*)buf.d + off_d, K, nvar, ncell);
+    } else {
+        pack_kernel<ffs, float><<<grid, 256, 0, s>>>(to_internal, ext, (ffs*)buf.u + off_u,
+                                                     (float*)buf.d + off_d, K, nvar, ncell);
     }
     return hipGetLastError();
 }

@@ -3,6 +3,7 @@
 // Jacobian-vector products, and the nonlinear weights.
 #pragma once
 
+#include "ff.h"
 #include "internal.h"
 
 namespace hweno {
@@ -16,6 +17,7 @@ template <int P> struct PrecT;
 template <> struct PrecT<P_F64> { using TU = double; using TD = double; using T = double; using TA = double; };
 template <> struct PrecT<P_F32> { using TU = float;  using TD = float;  using T = float;  using TA = float; };
 template <> struct PrecT<P_ACC64> { using TU = double; using TD = float; using T = float; using TA = double; };
+template <> struct PrecT<P_KAHAN> { using TU = ffs; using TD = float; using T = float; using TA = ff; };
 
 // Ghost cells as index maps: periodic wraps, transmissive clamps to the
 // nearest interior cell (every unknown of a ghost cell is that cell's).
@@ -44,6 +46,12 @@ template <int CTRL> __device__ __forceinline__ double dpp_shift(double v) {
     const int lo = dpp_shift<CTRL>(__double2loint(v));
     const int hi = dpp_shift<CTRL>(__double2hiint(v));
     return __hiloint2double(hi, lo);
+}
+template <int CTRL> __device__ __forceinline__ ffs dpp_shift(ffs v) {
+    ffs r;
+    r.hi = dpp_shift<CTRL>(v.hi);
+    r.lo = dpp_shift<CTRL>(v.lo);
+    return r;
 }
 template <class T> __device__ __forceinline__ T from_left(T v) { return dpp_shift<DPP_WAVE_SHR1>(v); }
 template <class T> __device__ __forceinline__ T from_right(T v) { return dpp_shift<DPP_WAVE_SHL1>(v); }

@@ -18,6 +18,7 @@ hipError_t launch_stage1d(int prec, int flux, int mode, const StageArgs& a, int 
     if (prec == P_F64) return dispatch1d<P_F64>(flux, mode, a, grid, s);
     if (prec == P_F32) return dispatch1d<P_F32>(flux, mode, a, grid, s);
     if (prec == P_ACC64) return dispatch1d<P_ACC64>(flux, mode, a, grid, s);
+    if (prec == P_KAHAN) return dispatch1d<P_KAHAN>(flux, mode, a, grid, s);
     return hipErrorInvalidValue;
 }
 

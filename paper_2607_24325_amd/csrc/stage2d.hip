@@ -6,6 +6,7 @@ namespace hweno {
 hipError_t launch_stage2d_f64(int flux, int Q, int mode, const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_stage2d_f32(int flux, int Q, int mode, const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_stage2d_acc64(int flux, int Q, int mode, const StageArgs& a, int grid, hipStream_t s);
+hipError_t launch_stage2d_kahan(int flux, int Q, int mode, const StageArgs& a, int grid, hipStream_t s);
 
 hipError_t launch_stage2d(int prec, int flux, int Q, int mode, const StageArgs& a, int grid,
                           hipStream_t s) {
@@ -14,6 +15,7 @@ hipError_t launch_stage2d(int prec, int flux, int Q, int mode, const StageArgs& 
     if (prec == P_F64) return launch_stage2d_f64(flux, Q, mode, a, grid, s);
     if (prec == P_F32) return launch_stage2d_f32(flux, Q, mode, a, grid, s);
     if (prec == P_ACC64) return launch_stage2d_acc64(flux, Q, mode, a, grid, s);
+    if (prec == P_KAHAN) return launch_stage2d_kahan(flux, Q, mode, a, grid, s);
     return hipErrorInvalidValue;
 }
 

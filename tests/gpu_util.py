@@ -53,9 +53,14 @@ def natural_scales(spec, st):
 
 
 def scaled_err(gpu, ref, scales):
-    """max over planes of max |gpu - ref| / scale of the plane"""
-    d = np.abs(np.asarray(gpu, dtype=np.float64) - np.asarray(ref, dtype=np.float64))
-    return float((d.max(axis=tuple(range(2, d.ndim))) / scales).max())
+    """max over planes of max |gpu - ref| / scale of the plane, the scale being
+    the larger of the given one and the plane's own magnitude in ref (a
+    derivative can grow by orders of magnitude in one step next to a jump)"""
+    g = np.asarray(gpu, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    ax = tuple(range(2, r.ndim))
+    d = np.abs(g - r).max(axis=ax)
+    return float((d / np.maximum(scales, np.abs(r).max(axis=ax))).max())
 
 
 def rhs_scales(spec, st, ax, ay):

@@ -30,7 +30,8 @@ def workload():
     return W.quadrant_vortex_2d(N, seed=7)
 
 
-@pytest.mark.parametrize("prec,tol", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-6), (hw.F32, 2e-6)])
+@pytest.mark.parametrize("prec,tol", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-6), (hw.F32_KAHAN, 2e-6),
+                                      (hw.F32, 2e-6)])
 def test_fullsize_step_sampled(workload, prec, tol):
     spec, st = workload
     cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)

@@ -129,7 +129,7 @@ def test_1d_advection_headline_run_to_time():
 
 # ------------------------------------------------------ reduced precision --
 
-@pytest.mark.parametrize("prec,tol", [(hw.F32, 2e-5), (hw.F32_ACC64, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(hw.F32, 2e-5), (hw.F32_ACC64, 2e-5), (hw.F32_KAHAN, 2e-5)])
 def test_2d_euler_step_reduced_precision(prec, tol):
     spec, st = W.quadrant_vortex_2d(96, seed=7)
     cfg = hw.default_config(2, precision=prec, gauss_q=2)
@@ -144,7 +144,7 @@ def test_2d_euler_step_reduced_precision(prec, tol):
     assert l1_rel(gpu[0], ref[0]) < tol, l1_rel(gpu[0], ref[0])
 
 
-@pytest.mark.parametrize("prec", [hw.F32, hw.F32_ACC64])
+@pytest.mark.parametrize("prec", [hw.F32, hw.F32_ACC64, hw.F32_KAHAN])
 def test_1d_euler_step_reduced_precision(prec):
     spec, st = W.riemann_1d(3, nx=600)
     cfg = hw.default_config(1, precision=prec)
@@ -159,11 +159,12 @@ def test_1d_euler_step_reduced_precision(prec):
     assert l1_rel(gpu[0], ref[0]) < 2e-5
 
 
-def test_acc64_conserves_cell_average_totals():
-    """FP32 reconstruction with FP64 flux differences and cell averages: the
-    periodic totals stay fixed to double rounding."""
+@pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F32_KAHAN])
+def test_mixed_precision_conserves_cell_average_totals(prec):
+    """FP32 reconstruction with FP64 (or compensated FP32) flux differences and
+    cell averages: the periodic totals stay fixed to ~double rounding."""
     spec, st = W.euler_2d_smooth(64)
-    cfg = hw.default_config(2, precision=hw.F32_ACC64, gauss_q=2)
+    cfg = hw.default_config(2, precision=prec, gauss_q=2)
     with _one(spec, st, cfg) as h:
         for _ in range(5):
             h.step()
