@@ -28,7 +28,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VEC_TFLOPS = 78.6         # MI355X vector FP64
+VEC_TFLOPS = 78.6              # MI355X vector FP64, = non-packed FP32 (FMA counted as 2)
+# FP operations per cell-stage of the 2D Euler stage (Q = 2), from the FP
+# instruction counters of the stage kernel restricted to output-producing
+# lanes and rows (profiles/stage2d_euler2048.md)
+ALU_FLOP_PER_CELL_STAGE = 2750.0
+# HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
+# the copy calibration) for the kernel sources of this hash; any change of
+# the sources invalidates them (reported as null until measured again).
+PROFILED_SOURCES = "dfc83f45d7b9875d"
+PROFILED_TRAFFIC = {"f32acc64": 816.5e6, "f64": 1228.7e6}
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    d = os.path.join(ROOT, "paper_2607_24325_amd", "csrc")
+    src = "".join(open(os.path.join(d, f)).read()
+                  for f in ("stage2d.h", "device_common.h", "ff.h", "internal.h"))
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
 def algorithmic_bytes_per_cell_stage(K: int, D: int, su: int, sd: int) -> float:
@@ -209,6 +226,8 @@ def main():
             batched[f"batched_{d}d"] = bench_batched(d, hw.F32_ACC64, args.steps, args.warmup, dev)
     B = main_r["bytes_per_cell_stage"]
     achieved = main_r["stage_hbm_gbs"]
+    alu_tflops = ALU_FLOP_PER_CELL_STAGE * ncell / (main_r["stage_kernel_ms"] * 1e-3) / 1e12
+    traffic = PROFILED_TRAFFIC["f32acc64"] if kernel_sources_hash() == PROFILED_SOURCES else None
     line = {
         "metric": "cell-stage updates/s (2D Euler 2048^2, FP32 vs FP64) + % HBM peak + L1 err",
         "value": main_r["value"],
@@ -225,9 +244,13 @@ def main():
         "config": {"workload": f"2D Euler {n}x{n} periodic, Q=2, CFL 0.5, quadrant+vortex seed 7",
                    "precision": "F32 bulk, FP64 cell averages and flux differences",
                    "cells": ncell, "unknowns_per_cell": 12},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "stage2d_kernel (F32_ACC64)", "algorithmic_bytes_per_cell_stage": B},
+        "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": VEC_TFLOPS, "unit": "TFLOP/s",
+                     "frac": alu_tflops / VEC_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
+                     "kernel": "stage2d_kernel (F32_ACC64)",
+                     "algorithmic_flop_per_cell_stage": ALU_FLOP_PER_CELL_STAGE,
+                     "hbm_achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes_per_cell_stage": B},
         "hbm_frac_fp64_path": f64_r["stage_hbm_gbs"] / HBM_PEAK_GBS,
         "fp64_path": {"value": f64_r["value"], "ms_per_step": f64_r["ms_per_step"],
                       "stage_kernel_ms": f64_r["stage_kernel_ms"],
