@@ -444,6 +444,7 @@ extern "C" int hweno_set_state(hweno_handle* h, int32_t prob, const double* src,
     d.err = 0;
     d.bad_cell = INT64_MAX;
     d.active = 0;
+    d.alpha_valid = 0;
     HIP_TRY(h, hipMemcpyAsync(h->d_probs + prob, &d, sizeof d, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->state_set[prob] = 1;
@@ -503,7 +504,7 @@ static hipError_t launch_stage(hweno_handle* h, int mode, const StageArgs& a) {
 }
 
 static int alpha_all(hweno_handle* h) {
-    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, h->stream));
+    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, 1, h->stream));
     HIP_TRY(h, launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
                             h->nchunks, h->sch, 1, 0, h->stream));
     return HWENO_OK;
@@ -558,7 +559,9 @@ extern "C" int hweno_rhs(hweno_handle* h, int32_t prob, double* L_out, double* U
 // One SSP-RK3 step of every unfinished problem: wave speeds and dt, three
 // fused stage kernels, time update.
 static int enqueue_step(hweno_handle* h, int use_dt_in) {
-    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, h->stream));
+    // speeds are gathered by stage 3 of the previous step; the reduction
+    // kernel only fills them in after set_state
+    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, 0, h->stream));
     HIP_TRY(h, launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
                             h->nchunks, h->sch, 0, 0, h->stream));
     HIP_TRY(h, launch_dt(h->d_probs, h->d_ctl, h->nprob, use_dt_in, h->stream));
@@ -761,7 +764,7 @@ extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* 
             return hipEventRecord(ev[k++], h->stream);
         };
         HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-        HIP_TRY(h, rec(launch_reset(h->d_probs, h->d_ctl, h->nprob, h->stream)));
+        HIP_TRY(h, rec(launch_reset(h->d_probs, h->d_ctl, h->nprob, 0, h->stream)));
         HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
         HIP_TRY(h, rec(launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs,
                                     h->d_chunks, h->nchunks, h->sch, 0, 0, h->stream)));

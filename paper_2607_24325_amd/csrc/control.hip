@@ -5,10 +5,11 @@
 
 namespace hweno {
 
-// Zeroes the wave-speed maxima of every problem and the step counters.
-__global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
+// Zeroes the wave-speed maxima that are about to be recomputed (all of
+// them, or those not current) and the step counters.
+__global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nprob) {
+    if (p < nprob && (all_problems || !probs[p].alpha_valid)) {
         probs[p].ax_bits = 0;
         probs[p].ay_bits = 0;
     }
@@ -16,21 +17,6 @@ __global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
         ctl->nactive = 0;
         ctl->step_active = 0;
     }
-}
-
-template <class T> __device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ long long wave_min_ll(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        long long w = __shfl_xor(v, o, 64);
-        v = w < v ? w : v;
-    }
-    return v;
 }
 
 // alpha_x = max |f'(u)|, alpha_y = max |g'(u)| over the cell averages of a
@@ -45,11 +31,10 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
     __shared__ double smx[4], smy[4];
     __shared__ long long sbad[4];
     const TU* U = (const TU*)uptr;
-    const double g = sch.gas_gamma;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const Chunk chunk = chunks[ch];
         ProbDev& P_ = probs[chunk.prob];
-        if (!all_problems && (!(P_.t < P_.t_end) || P_.err)) continue;
+        if (!all_problems && (!(P_.t < P_.t_end) || P_.err || P_.alpha_valid)) continue;
         const int64_t plane = (int64_t)P_.nx * P_.ny;
         const TU* base = U + P_.off_u;
         double mx = 0.0, my = 0.0;
@@ -57,38 +42,18 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
         for (int k = threadIdx.x; k < chunk.count; k += 256) {
             const int64_t idx = chunk.start + k;
             double u[K];
-            bool ok = true;
 #pragma unroll
-            for (int c = 0; c < K; ++c) {
-                u[c] = (double)base[c * plane + idx];
-                ok = ok && isfinite(u[c]);
-            }
-            double sx = 0.0, sy = 0.0;
-            if (FLUX == F_ADV) {
-                sx = fabs(sch.adv[0]);
-                sy = fabs(sch.adv[1]);
-            } else if (FLUX == F_BURGERS) {
-                sx = sy = fabs(u[0]);
-            } else {
-                const double rho = u[0];
-                const double vx = u[1] / rho;
-                const double vy = DIM == 2 ? u[2] / rho : 0.0;
-                const double ke = 0.5 * rho * (vx * vx + vy * vy);
-                const double pr = (g - 1.0) * (u[K - 1] - ke);
-                ok = ok && rho > 0.0 && pr > 0.0;
-                const double cs = ok ? sqrt(g * pr / rho) : 0.0;
-                sx = fabs(vx) + cs;
-                sy = fabs(vy) + cs;
-            }
-            if (ok) {
+            for (int c = 0; c < K; ++c) u[c] = (double)base[c * plane + idx];
+            double sx, sy;
+            if (wave_speed<FLUX, DIM, K>(u, sch, sx, sy)) {
                 mx = fmax(mx, sx);
                 my = fmax(my, sy);
             } else if (idx < bad) {
                 bad = idx;
             }
         }
-        mx = wave_max(mx);
-        my = wave_max(my);
+        mx = wave_max_d(mx);
+        my = wave_max_d(my);
         bad = wave_min_ll(bad);
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
@@ -143,11 +108,19 @@ __global__ void dt_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in
 
 // t += dt (exactly t_end on the clipped last step); counts problems still
 // running and the steps in which anything advanced.
+// The speeds stage 3 gathered from the new state become current.
 __global__ void finish_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < nprob) {
         ProbDev& P_ = probs[p];
-        if (P_.active) P_.t = P_.last ? P_.t_end : P_.t + P_.dt;
+        if (P_.active) {
+            P_.t = P_.last ? P_.t_end : P_.t + P_.dt;
+            P_.ax_bits = P_.ax_next;
+            P_.ay_bits = P_.ay_next;
+            P_.alpha_valid = 1;
+        }
+        P_.ax_next = 0;
+        P_.ay_next = 0;
         if (P_.t < P_.t_end && !P_.err) atomicAdd(&ctl->nactive, 1);
     }
     if (p == 0 && ctl->step_active) ctl->steps += 1;
@@ -174,8 +147,8 @@ __global__ void pack_kernel(int to_internal, double* ext, TU* u, TD* d, int K, i
 
 // --------------------------------------------------------------- launchers
 
-hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s) {
-    reset_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob);
+hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems, hipStream_t s) {
+    reset_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, all_problems);
     return hipGetLastError();
 }
 

@@ -160,6 +160,71 @@ template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
     }
 };
 
+// ------------------------------------------------------------ wave speeds --
+//
+// |f'(u)| and |g'(u)| at the cell average U (Euler: |velocity| + sound
+// speed), in double precision with no contraction, so that every kernel
+// that evaluates it produces the same bits; returns false if U is not
+// finite or (Euler) rho <= 0 or p <= 0.
+template <int FLUX, int DIM, int K>
+__device__ __forceinline__ bool wave_speed(const double* u, const Scheme& sch, double& sx,
+                                           double& sy) {
+#pragma clang fp contract(off)
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < K; ++c) ok = ok && isfinite(u[c]);
+    if (FLUX == F_ADV) {
+        sx = fabs(sch.adv[0]);
+        sy = fabs(sch.adv[1]);
+    } else if (FLUX == F_BURGERS) {
+        sx = sy = fabs(u[0]);
+    } else {
+        const double g = sch.gas_gamma;
+        const double rho = u[0];
+        const double vx = u[1] / rho;
+        const double vy = DIM == 2 ? u[2] / rho : 0.0;
+        const double ke = 0.5 * rho * (vx * vx + vy * vy);
+        const double pr = (g - 1.0) * (u[K - 1] - ke);
+        ok = ok && rho > 0.0 && pr > 0.0;
+        const double cs = ok ? sqrt(g * pr / rho) : 0.0;
+        sx = fabs(vx) + cs;
+        sy = fabs(vy) + cs;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ long long wave_min_ll(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// Folds one wave's speeds and first bad cell into the problem's slots for
+// the state being written (lane 0 issues the atomics).
+__device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, double my,
+                                                    long long bad) {
+    mx = wave_max_d(mx);
+    my = wave_max_d(my);
+    bad = wave_min_ll(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax((unsigned long long*)&P.ax_next, (unsigned long long)__double_as_longlong(mx));
+        atomicMax((unsigned long long*)&P.ay_next, (unsigned long long)__double_as_longlong(my));
+        if (bad != LLONG_MAX) {
+            atomicMin((long long*)&P.bad_cell, bad);
+            atomicOr(&P.err, 1);
+        }
+    }
+}
+
 // ----------------------------------------------------- nonlinear weights ---
 //
 // omega~_m = gamma_m (1 + tau^2 / D_m), omega = omega~ / sum (eq.

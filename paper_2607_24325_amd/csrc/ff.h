@@ -14,7 +14,7 @@ namespace hweno {
 struct ffs {
     float hi, lo;
     ffs() = default;
-    __host__ __device__ explicit ffs(double v) : hi((float)v), lo((float)(v - (double)(float)v)) {}
+    __host__ __device__ explicit ffs(double v) : hi((float)v), lo((float)(v - (double)hi)) {}
     __host__ __device__ explicit operator double() const { return (double)hi + (double)lo; }
     __host__ __device__ explicit operator float() const { return hi + lo; }
 };
@@ -23,13 +23,17 @@ struct ffs {
 // neighbouring averages are close, so hi - hi is exact (Sterbenz) or nearly.
 __device__ __forceinline__ float operator-(ffs a, ffs b) { return (a.hi - b.hi) + (a.lo - b.lo); }
 
+// Contraction is switched off in every routine below: fused forms of these
+// exact-rounding-error expressions would cancel the error terms.
 __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
     s = a + b;
     const float bp = s - a;
     e = (a - (s - bp)) + (b - bp);
 }
 
 __device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+#pragma clang fp contract(off)
     s = a + b;
     e = b - (s - a);
 }
@@ -41,7 +45,7 @@ struct ff {
     __device__ ff(int v) : hi((float)v), lo(0.f) {}
     __device__ ff(float v) : hi(v), lo(0.f) {}
     __device__ ff(float h, float l) : hi(h), lo(l) {}
-    __device__ explicit ff(double v) : hi((float)v), lo((float)(v - (double)(float)v)) {}
+    __device__ explicit ff(double v) : hi((float)v), lo((float)(v - (double)hi)) {}
     __device__ explicit ff(ffs s) : hi(s.hi), lo(s.lo) {}
     __device__ explicit operator float() const { return hi + lo; }
     __device__ explicit operator double() const { return (double)hi + (double)lo; }
@@ -55,6 +59,7 @@ struct ff {
 __device__ __forceinline__ ff operator-(ff a) { return ff(-a.hi, -a.lo); }
 
 __device__ __forceinline__ ff operator+(ff a, ff b) {
+#pragma clang fp contract(off)
     float s, e;
     two_sum(a.hi, b.hi, s, e);
     e += a.lo + b.lo;
@@ -66,6 +71,7 @@ __device__ __forceinline__ ff operator+(ff a, ff b) {
 __device__ __forceinline__ ff operator-(ff a, ff b) { return a + (-b); }
 
 __device__ __forceinline__ ff operator*(ff a, ff b) {
+#pragma clang fp contract(off)
     const float p = a.hi * b.hi;
     float e = fmaf(a.hi, b.hi, -p);
     e += a.hi * b.lo + a.lo * b.hi;

@@ -30,12 +30,14 @@ struct ProbDev {
     double t, t_end;
     double dt;         // step being taken (0 when inactive)
     double dt_in;      // requested step when the caller supplies one
-    uint64_t ax_bits;  // max wave speeds, as the bits of non-negative doubles
-    uint64_t ay_bits;
+    uint64_t ax_bits;  // max wave speeds of the current state, as the bits of
+    uint64_t ay_bits;  // non-negative doubles
+    uint64_t ax_next;  // the same for the state stage 3 is writing
+    uint64_t ay_next;
     int32_t active;    // 1 while the current step advances this problem
     int32_t last;      // the current step lands exactly on t_end
     int32_t err;       // non-admissible state seen
-    int32_t pad;
+    int32_t alpha_valid;  // ax_bits/ay_bits hold the speeds of the current state
     int64_t bad_cell;  // smallest flat index of a non-admissible cell
 };
 
@@ -106,9 +108,12 @@ hipError_t launch_stage1d(int prec, int flux, int mode, const StageArgs& a, int 
                           hipStream_t s);
 hipError_t launch_stage2d(int prec, int flux, int Q, int mode, const StageArgs& a, int grid,
                           hipStream_t s);
-hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s);
+// all_problems: zero the speeds of every problem (queries), or only of those
+// whose speeds are not current (time stepping).
+hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems, hipStream_t s);
 // all_problems: 1 = every problem (rhs / alpha queries); 0 = only problems
-// still short of t_end and without a pending error (time stepping).
+// still short of t_end, without a pending error and whose speeds are not
+// current (time stepping: stage 3 computes them for the next step).
 hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* probs,
                         const Chunk* chunks, int nchunks, const Scheme& sch, int all_problems,
                         int grid, hipStream_t s);

@@ -117,7 +117,9 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
 
         // ---- residual and RK stage of local cell tid -----------------------
         const int gi = c0 - 1 + tid;
-        if (tid >= 1 && tid <= TILE1D_OUT && gi < nx) {
+        const bool emit = tid >= 1 && tid <= TILE1D_OUT && gi < nx;
+        double unew[K];
+        if (emit) {
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const TA Lu = -((TA)sF[c][tid] - (TA)sF[c][tid - 1]) * inv_dx_a;
@@ -147,12 +149,29 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
                             Ou[ou] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
                             Ov[od] = (TD)((T)0.75 * hn + (T)0.25 * (vhat[c] + dtt * Lv));
                         } else {
-                            Ou[ou] = (TU)((TA)(1.0 / 3.0) * unr + (TA)(2.0 / 3.0) * (ucur + dta * Lu));
+                            const TU nu = (TU)((TA)(1.0 / 3.0) * unr + (TA)(2.0 / 3.0) * (ucur + dta * Lu));
+                            Ou[ou] = nu;
+                            unew[c] = (double)nu;
                             Ov[od] = (TD)((T)(1.0 / 3.0) * hn + (T)(2.0 / 3.0) * (vhat[c] + dtt * Lv));
                         }
                     }
                 }
             }
+        }
+        if (mode == MODE_S3) {
+            // wave speeds of the state being written, for the next step
+            double mx = 0.0, my = 0.0;
+            long long bad = LLONG_MAX;
+            if (emit) {
+                double sx, sy;
+                if (wave_speed<FLUX, 1, K>(unew, sch, sx, sy)) {
+                    mx = sx;
+                    my = sy;
+                } else {
+                    bad = gi;
+                }
+            }
+            publish_next_speeds(a.probs[tile.prob], mx, my, bad);
         }
         __syncthreads();   // LDS reuse by the next tile
     }

@@ -176,8 +176,8 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
     }
 }
 
-template <int P, int K, int Q, int FLUX>
-__global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) {
+template <int P, int K, int Q, int FLUX, int mode>
+__global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
@@ -185,6 +185,9 @@ __global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) 
     constexpr int NF = Q * 3 * K;  // face values per lane and face (all components)
     __shared__ T sxR[NF][64], sxL[NF][64], syB[NF][64], syT[NF][64];
     __shared__ T sFX[Q][3 * K][64], sFY[Q][3 * K][64];
+    __shared__ double snew[K][64];   // stage 3: new cell averages of the output row
+    __shared__ double smx[64], smy[64];   // stage 3: per-lane maxima of the wave speeds
+    __shared__ long long sbad[64];        // stage 3: per-lane first non-admissible cell
 
     const int lane = threadIdx.x & 63;
     const int c = threadIdx.x >> 6;  // component of this wave
@@ -215,6 +218,32 @@ __global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) 
 
         auto row_ptr = [&](int j) { return (int64_t)bc_map(j, ny, bcy) * nx + li; };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
+
+        // Stage 3 also gathers the wave speeds of the state it writes (for the
+        // next step's flux and time step): wave 0 reads the four new averages of
+        // each output cell from LDS one barrier after they were written and
+        // keeps per-lane maxima in LDS (no registers live across the march).
+        constexpr bool fuse_alpha = mode == MODE_S3;
+        if (fuse_alpha && c == 0) {
+            smx[lane] = 0.0;
+            smy[lane] = 0.0;
+            sbad[lane] = LLONG_MAX;
+        }
+        auto gather_speeds = [&](int row) {
+            if (c == 0 && out_col) {
+                double u[K];
+#pragma unroll
+                for (int k = 0; k < K; ++k) u[k] = snew[k][lane];
+                double sx, sy;
+                if (wave_speed<FLUX, 2, K>(u, sch, sx, sy)) {
+                    smx[lane] = fmax(smx[lane], sx);
+                    smy[lane] = fmax(smy[lane], sy);
+                } else {
+                    const long long idx = (long long)row * nx + gi;
+                    if (idx < sbad[lane]) sbad[lane] = idx;
+                }
+            }
+        };
 
         TU um, u0, up, un_;
         TD vm, v0, vp, vn_, wm, w0, wp, wn_;
@@ -306,6 +335,7 @@ __global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) 
 
             if (r > j0 - 1) {
                 __syncthreads();  // A: face values of row r (and top faces of r-1) ready
+                if (fuse_alpha && r > j0 + 1) gather_speeds(r - 2);
                 // ---- F: edge fluxes ---------------------------------------
                 for (int sl = threadIdx.x; sl < 2 * Q * 64; sl += 64 * K) {
                     const int kind = sl / (Q * 64);
@@ -391,7 +421,9 @@ __global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) 
                                 Ow[oo] = (TD)((T)0.75 * hwr + (T)0.25 * (hat_prev[1] + dtt * Lw));
                             } else {
                                 const TA third = (TA)(1.0 / 3.0), two3 = (TA)(2.0 / 3.0);
-                                Ou[oo] = (TU)(third * unr + two3 * (ucur + dta * Lu));
+                                const TU nu = (TU)(third * unr + two3 * (ucur + dta * Lu));
+                                Ou[oo] = nu;
+                                snew[c][lane] = (double)nu;
                                 Ov[oo] = (TD)((T)(1.0 / 3.0) * hvr +
                                               (T)(2.0 / 3.0) * (hat_prev[0] + dtt * Lv));
                                 Ow[oo] = (TD)((T)(1.0 / 3.0) * hwr +
@@ -414,6 +446,10 @@ __global__ void __launch_bounds__(64 * K) stage2d_kernel(StageArgs a, int mode) 
             wm = w0; w0 = wp; wp = wn_;
         }
         __syncthreads();  // LDS reuse by the next tile
+        if (fuse_alpha) {
+            gather_speeds(jend - 1);
+            if (c == 0) publish_next_speeds(a.probs[tile.prob], smx[lane], smy[lane], sbad[lane]);
+        }
     }
 }
 

@@ -239,7 +239,22 @@ class Handle:
         self._check(lib().hweno_autotune(self.h, C.byref(t)))
         return t
 
-    def timed_steps(self, nsteps: int) -> hweno_timing:
+    def timed_steps(self, nsteps: int, allow_nonfinite: bool = False) -> hweno_timing:
+        """Per-kernel timing of nsteps eager steps.  With allow_nonfinite, a
+        problem that became non-admissible (and was frozen) does not raise:
+        the timing of the steps that ran is returned."""
         t = hweno_timing()
-        self._check(lib().hweno_timed_steps(self.h, nsteps, C.byref(t)))
+        rc = lib().hweno_timed_steps(self.h, nsteps, C.byref(t))
+        if not (allow_nonfinite and rc == ERR_NONFINITE):
+            self._check(rc)
         return t
+
+    def failed_problems(self):
+        """Indices of the problems frozen because their state became
+        non-admissible."""
+        bad = []
+        for i in range(len(self.specs)):
+            t = C.c_double()
+            if lib().hweno_get_state(self.h, i, None, 0, C.byref(t)) == ERR_NONFINITE:
+                bad.append(i)
+        return bad

@@ -245,3 +245,34 @@ def test_nonadmissible_state_is_reported():
         assert ei.value.code == hw.ERR_NONFINITE and "i=123" in str(ei.value)
         with pytest.raises(hw.HwenoError):
             h.get_state(0)
+
+
+def test_nonadmissible_state_reached_by_the_scheme_matches_oracle():
+    """Problem 1390 of the seeded 4096-problem 1D batch (four Riemann states)
+    develops a non-admissible state after 74 steps (the scheme has no
+    positivity limiter): the GPU reports the same step, time and cell as the
+    oracle, and keeps the state of the last admissible step."""
+    entries = W.batched_1d(seed=1, nprob=4096)
+    spec, st = entries[1390][0], W.batched_1d_state(entries[1390])
+    cfg = hw.default_config(1, precision=hw.F64)
+    p = oproblem(spec, cfg)
+    cur, t, n = st, 0.0, 0
+    while True:
+        try:
+            ax, _ = O.alpha(p, cur)
+        except O.OracleError as e:
+            bad_msg = str(e)
+            break
+        dt = O.dt(p, ax, 0.0, cfg.cfl)
+        cur = O.step(p, cur, ax, 0.0, dt)
+        t += dt
+        n += 1
+    cell = int(bad_msg.split()[-1])
+    with _one(spec, st, cfg) as h:
+        with pytest.raises(hw.HwenoError) as ei:
+            h.run_to_time()
+        assert ei.value.code == hw.ERR_NONFINITE
+        assert f"i={cell} " in str(ei.value)
+        t_gpu = float(str(ei.value).split("t=")[-1])
+        assert abs(t_gpu - t) <= 1e-12 * t
+        assert n == 74
