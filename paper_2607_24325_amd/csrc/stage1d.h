@@ -14,8 +14,8 @@
 
 namespace hweno {
 
-template <int P, int K, int FLUX>
-__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
+template <int P, int K, int FLUX, int mode>
+__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
@@ -26,6 +26,8 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
     __shared__ T sR[2 * K][256];         // (u, u_x) at x_{i+1/2} from cell i
     __shared__ T sL[2 * K][256];         // (u, u_x) at x_{i-1/2} from cell i
     __shared__ T sF[2 * K][256];         // (f-hat, h-hat) at the right interface of cell t
+    __shared__ double s_mx[4], s_my[4];  // stage 3: per-wave maxima of the wave speeds
+    __shared__ long long s_bad[4];
 
     const int tid = threadIdx.x;
     const Scheme& sch = a.sch;
@@ -159,7 +161,8 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
             }
         }
         if (mode == MODE_S3) {
-            // wave speeds of the state being written, for the next step
+            // wave speeds of the state being written, for the next step:
+            // reduced over the wave here and over the workgroup below
             double mx = 0.0, my = 0.0;
             long long bad = LLONG_MAX;
             if (emit) {
@@ -171,9 +174,22 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a, int mode) {
                     bad = gi;
                 }
             }
-            publish_next_speeds(a.probs[tile.prob], mx, my, bad);
+            mx = wave_max_d(mx);
+            my = wave_max_d(my);
+            bad = wave_min_ll(bad);
+            if ((tid & 63) == 0) {
+                s_mx[tid >> 6] = mx;
+                s_my[tid >> 6] = my;
+                s_bad[tid >> 6] = bad;
+            }
         }
         __syncthreads();   // LDS reuse by the next tile
+        if (mode == MODE_S3 && tid < 64) {
+            const double mx = tid < 4 ? s_mx[tid] : 0.0;
+            const double my = tid < 4 ? s_my[tid] : 0.0;
+            const long long bad = tid < 4 ? s_bad[tid] : LLONG_MAX;
+            publish_next_speeds(a.probs[tile.prob], mx, my, bad);
+        }
     }
 }
 

@@ -3,11 +3,21 @@
 
 namespace hweno {
 
+template <int P, int K, int FLUX>
+static void launch_modes(int mode, const StageArgs& a, int grid, hipStream_t s) {
+    switch (mode) {
+        case MODE_RHS: stage1d_kernel<P, K, FLUX, MODE_RHS><<<grid, 256, 0, s>>>(a); break;
+        case MODE_S1: stage1d_kernel<P, K, FLUX, MODE_S1><<<grid, 256, 0, s>>>(a); break;
+        case MODE_S2: stage1d_kernel<P, K, FLUX, MODE_S2><<<grid, 256, 0, s>>>(a); break;
+        default: stage1d_kernel<P, K, FLUX, MODE_S3><<<grid, 256, 0, s>>>(a); break;
+    }
+}
+
 template <int P>
 static hipError_t dispatch1d(int flux, int mode, const StageArgs& a, int grid, hipStream_t s) {
-    if (flux == F_ADV) stage1d_kernel<P, 1, F_ADV><<<grid, 256, 0, s>>>(a, mode);
-    else if (flux == F_BURGERS) stage1d_kernel<P, 1, F_BURGERS><<<grid, 256, 0, s>>>(a, mode);
-    else stage1d_kernel<P, 3, F_EULER><<<grid, 256, 0, s>>>(a, mode);
+    if (flux == F_ADV) launch_modes<P, 1, F_ADV>(mode, a, grid, s);
+    else if (flux == F_BURGERS) launch_modes<P, 1, F_BURGERS>(mode, a, grid, s);
+    else launch_modes<P, 3, F_EULER>(mode, a, grid, s);
     return hipGetLastError();
 }
 

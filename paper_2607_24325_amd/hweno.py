@@ -14,7 +14,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libhweno.so")
+# HWENO_LIB selects another build of the same library (e.g. to compare builds)
+LIB_PATH = os.environ.get("HWENO_LIB", os.path.join(PKG, "libhweno.so"))
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_HIP, ERR_STATE, ERR_OOM = 0, -1, -2, -3, -4, -5
 ADVECTION, BURGERS, EULER = 0, 1, 2
