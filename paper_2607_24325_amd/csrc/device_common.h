@@ -33,9 +33,11 @@ __device__ __forceinline__ double as_double(uint64_t b) { return __longlong_as_d
 
 // Whole-wave lane shifts through DPP (wave_shr:1 / wave_shl:1 of the GFX9
 // data-parallel primitives): lane l receives lane l-1 (from_left) or lane l+1
-// (from_right); the lane at the end of the wave keeps its own value.
+// (from_right); the lane at the end of the wave, which has no source, gets 0
+// (bound_ctrl), so the shift is a single v_mov_b32_dpp.  Callers never use the
+// end lanes' results.
 template <int CTRL> __device__ __forceinline__ int dpp_shift(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 constexpr int DPP_WAVE_SHL1 = 0x130;
 constexpr int DPP_WAVE_SHR1 = 0x138;
