@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libhweno_oracle.so")
 SRC_PATH = os.path.join(HERE, "hweno_oracle.c")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 W_PAPER, W_BETA, W_BETA2, W_LINEAR = 0, 1, 2, 3
 
 
@@ -44,7 +44,7 @@ class _Problem(C.Structure):
                 ("yhi", C.c_double), ("bc_x", C.c_int), ("bc_y", C.c_int),
                 ("gas_gamma", C.c_double), ("adv", C.c_double * 2),
                 ("gauss_q", C.c_int), ("weights", C.c_int),
-                ("gamma_lin", C.c_double * 5), ("eps", C.c_double)]
+                ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("charwise", C.c_int)]
 
 
 @dataclass
@@ -65,6 +65,7 @@ class Problem:
     weights: int = W_PAPER
     gamma_lin: tuple = field(default=None)
     eps: float = 1e-8
+    charwise: int = 0
 
     def __post_init__(self):
         if self.gamma_lin is None:
@@ -98,7 +99,7 @@ class Problem:
         return _Problem(self.dim, self.flux, self.nx, self.ny, self.xlo, self.xhi,
                         self.ylo, self.yhi, self.bc_x, self.bc_y, self.gas_gamma,
                         (C.c_double * 2)(*self.adv), self.gauss_q, self.weights,
-                        (C.c_double * 5)(*g), self.eps)
+                        (C.c_double * 5)(*g), self.eps, int(self.charwise))
 
 
 _lib = None
@@ -114,6 +115,9 @@ def lib():
         P = C.POINTER(_Problem)
         L.orc_recon_1d.argtypes = [P, _D, _D, C.c_double, _D]
         L.orc_recon_2d.argtypes = [P, _D, _D]
+        L.orc_euler_eigen.argtypes = [P, C.c_int, _D, _D, _D, _D]
+        L.orc_recon_char_1d.argtypes = [P, _D, _D, C.c_double, _D]
+        L.orc_recon_char_2d.argtypes = [P, _D, C.c_int, _D]
         L.orc_poly2d_eval.argtypes = [_D, C.c_double, C.c_double, _D]
         L.orc_poly2d_eval.restype = None
         L.orc_flux.argtypes = [P, C.c_int, _D, _D, _D, _D]
@@ -178,6 +182,41 @@ def recon_2d(p: Problem, q) -> dict:
     _check(lib().orc_recon_2d(C.byref(pc), _ptr(q), _ptr(out)), "recon_2d")
     return {"c0": out[0:15], "lin": out[15:27].reshape(4, 3), "beta": out[27:32],
             "omega": out[32:37], "C": out[37:52], "vhat": out[52], "what": out[53]}
+
+
+def euler_eigen(p: Problem, direction: int, U):
+    """(R, L, lam): right eigenvectors as the columns of R, L = R^-1, eigenvalues."""
+    U = _f64(U)
+    R = np.zeros((p.K, p.K))
+    L = np.zeros((p.K, p.K))
+    lam = np.zeros(p.K)
+    pc = p._c()
+    _check(lib().orc_euler_eigen(C.byref(pc), direction, _ptr(U), _ptr(R), _ptr(L), _ptr(lam)),
+           "euler_eigen")
+    return R, L, lam
+
+
+def recon_char_1d(p: Problem, ub, vb, dx: float) -> dict:
+    """ub (3, K): cells i-1, i, i+1; vb (2, K): derivative means of i-1, i+1."""
+    ub, vb = _f64(ub), _f64(vb)
+    assert ub.shape == (3, p.K) and vb.shape == (2, p.K)
+    out = np.zeros(6 * p.K)
+    pc = p._c()
+    _check(lib().orc_recon_char_1d(C.byref(pc), _ptr(ub), _ptr(vb), dx, _ptr(out)),
+           "recon_char_1d")
+    return {"C": out[:5 * p.K].reshape(p.K, 5), "vhat": out[5 * p.K:]}
+
+
+def recon_char_2d(p: Problem, q, direction: int) -> dict:
+    """q (17, K): the stencil of recon_2d, one K-vector per entry."""
+    q = _f64(q)
+    assert q.shape == (17, p.K)
+    out = np.zeros(17 * p.K)
+    pc = p._c()
+    _check(lib().orc_recon_char_2d(C.byref(pc), _ptr(q), direction, _ptr(out)),
+           "recon_char_2d")
+    K = p.K
+    return {"C": out[:15 * K].reshape(K, 15), "vhat": out[15 * K:16 * K], "what": out[16 * K:]}
 
 
 def poly2d_eval(Cc, xi: float, eta: float) -> np.ndarray:

@@ -405,6 +405,175 @@ int orc_recon_2d(const orc_problem* p, const double q[17], double* out) {
     return 0;
 }
 
+/* ======================================================================
+ * Local characteristic variables for the Euler equations (the remark that
+ * closes Sec. 2.2: for systems, reconstruction and modification run in the
+ * local characteristic directions)
+ * ====================================================================== */
+
+int orc_euler_eigen(const orc_problem* p, int dir, const double* U, double* R, double* L,
+                    double* lam) {
+    if (p->flux != ORC_EULER) return -1;
+    double g = p->gas_gamma;
+    int K = orc_ncomp(p);
+    double rho = U[0];
+    /* normal and tangential velocity; in 2D the normal momentum is component
+     * 1 + dir and the tangential one 2 - dir */
+    int in = 1, it = 2;
+    if (K == 4 && dir == 1) { in = 2; it = 1; }
+    double vn = U[in] / rho;
+    double vt = K == 4 ? U[it] / rho : 0.0;
+    double q2 = vn * vn + vt * vt;
+    double pr = (g - 1.0) * (U[K - 1] - 0.5 * rho * q2);
+    double c = sqrt(g * pr / rho);
+    double H = (U[K - 1] + pr) / rho;
+    double b1 = (g - 1.0) / (c * c);
+    double b2 = 0.5 * b1 * q2;
+    for (int k = 0; k < K * K; ++k) R[k] = L[k] = 0.0;
+    if (K == 3) {
+        /* columns: v - c, v, v + c */
+        double r[3][3] = {{1.0, 1.0, 1.0}, {vn - c, vn, vn + c}, {H - vn * c, 0.5 * q2, H + vn * c}};
+        double l[3][3] = {{0.5 * (b2 + vn / c), -0.5 * (b1 * vn + 1.0 / c), 0.5 * b1},
+                          {1.0 - b2, b1 * vn, -b1},
+                          {0.5 * (b2 - vn / c), -0.5 * (b1 * vn - 1.0 / c), 0.5 * b1}};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                R[a * 3 + b] = r[a][b];
+                L[a * 3 + b] = l[a][b];
+            }
+        lam[0] = vn - c; lam[1] = vn; lam[2] = vn + c;
+        return 0;
+    }
+    /* 2D, in the component order (rho, normal momentum, tangential momentum,
+     * E); columns: v_n - c, entropy v_n, shear v_n, v_n + c */
+    double r[4][4] = {{1.0, 1.0, 0.0, 1.0},
+                      {vn - c, vn, 0.0, vn + c},
+                      {vt, vt, 1.0, vt},
+                      {H - vn * c, 0.5 * q2, vt, H + vn * c}};
+    double l[4][4] = {{0.5 * (b2 + vn / c), -0.5 * (b1 * vn + 1.0 / c), -0.5 * b1 * vt, 0.5 * b1},
+                      {1.0 - b2, b1 * vn, b1 * vt, -b1},
+                      {-vt, 0.0, 1.0, 0.0},
+                      {0.5 * (b2 - vn / c), -0.5 * (b1 * vn - 1.0 / c), -0.5 * b1 * vt, 0.5 * b1}};
+    /* (rho, normal, tangential, E) -> storage component index */
+    int map[4] = {0, in, it, 3};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            R[map[a] * 4 + b] = r[a][b];   /* rows of R are components */
+            L[a * 4 + map[b]] = l[a][b];   /* columns of L are components */
+        }
+    lam[0] = vn - c; lam[1] = vn; lam[2] = vn; lam[3] = vn + c;
+    return 0;
+}
+
+static double dotk(const double* a, const double* b, int K) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += a[k] * b[k];
+    return s;
+}
+
+/* 1D cell in characteristic variables: C[c][l] physical coefficients and
+ * vh[c] the physical modified derivative.  Scalar laws: per component. */
+static void char_recon_1d(const orc_problem* p, const double* ub, const double* vb, double dx,
+                          double C[4][5], double vh[4]) {
+    int K = orc_ncomp(p);
+    if (p->flux != ORC_EULER || !p->charwise) {
+        for (int c = 0; c < K; ++c) {
+            double s[3] = {ub[c], ub[K + c], ub[2 * K + c]};
+            recon1d_t r;
+            recon_1d(p, s, vb[c], vb[K + c], dx, &r);
+            memcpy(C[c], r.C, sizeof(r.C));
+            vh[c] = r.vhat;
+        }
+        return;
+    }
+    double R[16], L[16], lam[4];
+    orc_euler_eigen(p, 0, ub + K, R, L, lam);   /* the cell's own average */
+    double Cw[4][5], vw[4];
+    for (int k = 0; k < K; ++k) {
+        const double* lk = L + k * K;
+        double s[3] = {dotk(lk, ub, K), dotk(lk, ub + K, K), dotk(lk, ub + 2 * K, K)};
+        recon1d_t r;
+        recon_1d(p, s, dotk(lk, vb, K), dotk(lk, vb + K, K), dx, &r);
+        memcpy(Cw[k], r.C, sizeof(r.C));
+        vw[k] = r.vhat;
+    }
+    for (int c = 0; c < K; ++c) {
+        for (int l = 0; l < 5; ++l) {
+            double a = 0.0;
+            for (int k = 0; k < K; ++k) a += R[c * K + k] * Cw[k][l];
+            C[c][l] = a;
+        }
+        double a = 0.0;
+        for (int k = 0; k < K; ++k) a += R[c * K + k] * vw[k];
+        vh[c] = a;
+    }
+}
+
+int orc_recon_char_1d(const orc_problem* p, const double* ub, const double* vb, double dx,
+                      double* out) {
+    int K = orc_ncomp(p);
+    double C[4][5], vh[4];
+    char_recon_1d(p, ub, vb, dx, C, vh);
+    for (int c = 0; c < K; ++c)
+        for (int l = 0; l < 5; ++l) out[c * 5 + l] = C[c][l];
+    for (int c = 0; c < K; ++c) out[5 * K + c] = vh[c];
+    return 0;
+}
+
+/* 2D cell in the characteristic variables of direction dir (scalar laws and
+ * charwise = 0: per component, dir ignored).  q[s*K + c]. */
+static void char_recon_2d(const orc_problem* p, const double* q, int dir, double C[4][15],
+                          double vh[4], double wh[4]) {
+    int K = orc_ncomp(p);
+    int ch = p->flux == ORC_EULER && p->charwise;
+    double R[16], L[16], lam[4];
+    if (ch) orc_euler_eigen(p, dir, q + 4 * K, R, L, lam);   /* stencil entry 5: the cell */
+    double Cw[4][15], vw[4], ww[4];
+    for (int k = 0; k < K; ++k) {
+        double s[17];
+        for (int e = 0; e < 17; ++e) s[e] = ch ? dotk(L + k * K, q + e * K, K) : q[e * K + k];
+        recon2d_t r;
+        recon_2d(p, s, &r);
+        memcpy(Cw[k], r.C, sizeof(r.C));
+        vw[k] = r.vhat;
+        ww[k] = r.what;
+    }
+    for (int c = 0; c < K; ++c) {
+        if (!ch) {
+            memcpy(C[c], Cw[c], sizeof(Cw[c]));
+            vh[c] = vw[c];
+            wh[c] = ww[c];
+            continue;
+        }
+        for (int l = 0; l < 15; ++l) {
+            double a = 0.0;
+            for (int k = 0; k < K; ++k) a += R[c * K + k] * Cw[k][l];
+            C[c][l] = a;
+        }
+        double a = 0.0, b = 0.0;
+        for (int k = 0; k < K; ++k) {
+            a += R[c * K + k] * vw[k];
+            b += R[c * K + k] * ww[k];
+        }
+        vh[c] = a;
+        wh[c] = b;
+    }
+}
+
+int orc_recon_char_2d(const orc_problem* p, const double* q, int dir, double* out) {
+    int K = orc_ncomp(p);
+    double C[4][15], vh[4], wh[4];
+    char_recon_2d(p, q, dir, C, vh, wh);
+    for (int c = 0; c < K; ++c)
+        for (int l = 0; l < 15; ++l) out[c * 15 + l] = C[c][l];
+    for (int c = 0; c < K; ++c) {
+        out[15 * K + c] = vh[c];
+        out[16 * K + c] = wh[c];
+    }
+    return 0;
+}
+
+
 /* Gauss-Legendre nodes on [-1/2, 1/2] with weights summing to one */
 static int gauss_rule(int Q, double* node, double* wt) {
     if (Q == 1) {
@@ -455,9 +624,31 @@ static int bc_map(int i, int n, int bc) {
         int r = i % n;
         return r < 0 ? r + n : r;
     }
+    if (bc == ORC_REFLECTIVE) {
+        /* mirror images across both walls: period 2n, folded */
+        int r = i % (2 * n);
+        if (r < 0) r += 2 * n;
+        return r < n ? r : 2 * n - 1 - r;
+    }
     if (i < 0) return 0;
     if (i >= n) return n - 1;
     return i;
+}
+
+/* Sign with which the unknown (var v, component c) of a cell is taken into
+ * the ghost position i of an axis (0 = x, 1 = y).  Across a solid wall the
+ * mirror image of the flow has the normal velocity reversed: the normal
+ * momentum is odd and every other conserved quantity even, and the mean of
+ * the derivative along the axis (v-bar for x, w-bar for y) has the opposite
+ * parity of its quantity.  An odd number of reflections applies the sign. */
+static double bc_sign(const orc_problem* p, int axis, int i, int n, int v, int c) {
+    int bc = axis == 0 ? p->bc_x : p->bc_y;
+    if (bc != ORC_REFLECTIVE) return 1.0;
+    int r = i % (2 * n);
+    if (r < 0) r += 2 * n;
+    if (r < n) return 1.0;
+    double s = (p->flux == ORC_EULER && c == 1 + axis) ? -1.0 : 1.0;
+    return v == 1 + axis ? -s : s;
 }
 
 /* fill ext (margins gx, gy) from the full-grid state: window origin (i0, j0) */
@@ -470,9 +661,11 @@ static void fill_from_state(const orc_problem* p, const double* st, ext_t* e, in
             const double* src = st + (size_t)(v * e->K + c) * nx * ny;
             for (int jj = 0; jj < e->nye; ++jj) {
                 int j = p->dim == 1 ? 0 : bc_map(j0 + jj - gy, ny, p->bc_y);
+                double sy = p->dim == 1 ? 1.0 : bc_sign(p, 1, j0 + jj - gy, ny, v, c);
                 for (int ii = 0; ii < e->nxe; ++ii) {
                     int i = bc_map(i0 + ii - gx, nx, p->bc_x);
-                    dst[(size_t)jj * e->nxe + ii] = src[(size_t)j * nx + i];
+                    double sx = bc_sign(p, 0, i0 + ii - gx, nx, v, c);
+                    dst[(size_t)jj * e->nxe + ii] = sx * sy * src[(size_t)j * nx + i];
                 }
             }
         }
@@ -487,11 +680,13 @@ static void ghost_fill(const orc_problem* p, ext_t* e, int gx, int gy) {
             double* a = ext_at(e, v, c);
             for (int jj = 0; jj < e->nye; ++jj) {
                 int j = p->dim == 1 ? 0 : bc_map(jj - gy, ny, p->bc_y);
+                double sy = p->dim == 1 ? 1.0 : bc_sign(p, 1, jj - gy, ny, v, c);
                 for (int ii = 0; ii < e->nxe; ++ii) {
                     int i = bc_map(ii - gx, nx, p->bc_x);
                     int inside = (ii - gx == i) && (p->dim == 1 || jj - gy == j);
                     if (!inside)
-                        a[(size_t)jj * e->nxe + ii] = a[(size_t)(j + gy) * e->nxe + (i + gx)];
+                        a[(size_t)jj * e->nxe + ii] = bc_sign(p, 0, ii - gx, nx, v, c) * sy *
+                                                      a[(size_t)(j + gy) * e->nxe + (i + gx)];
                 }
             }
         }
@@ -521,16 +716,23 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
 #pragma omp parallel for num_threads(nthreads) schedule(static)
         for (int t = 0; t < nc; ++t) {
             int i = xa - 1 + t;
+            double s[12], w[8];
             for (int c = 0; c < K; ++c) {
-                double* ub = ext_at(U, 0, c);
-                double* vb = ext_at(U, 1, c);
-                double s[3] = {ub[i - 1], ub[i], ub[i + 1]};
-                recon1d_t r;
-                recon_1d(p, s, vb[i - 1], vb[i + 1], dx, &r);
+                const double* ub = ext_at(U, 0, c);
+                const double* vb = ext_at(U, 1, c);
+                s[c] = ub[i - 1];
+                s[K + c] = ub[i];
+                s[2 * K + c] = ub[i + 1];
+                w[c] = vb[i - 1];
+                w[K + c] = vb[i + 1];
+            }
+            double Cc[4][5], vc[4];
+            char_recon_1d(p, s, w, dx, Cc, vc);
+            for (int c = 0; c < K; ++c) {
                 double* o = um + ((size_t)t * K + c) * 4;
-                poly1d_eval(r.C, 0.5, dx, &o[0], &o[2]);
-                poly1d_eval(r.C, -0.5, dx, &o[1], &o[3]);
-                vh[(size_t)t * K + c] = r.vhat;
+                poly1d_eval(Cc[c], 0.5, dx, &o[0], &o[2]);
+                poly1d_eval(Cc[c], -0.5, dx, &o[1], &o[3]);
+                vh[(size_t)t * K + c] = vc[c];
             }
         }
         /* interface fluxes (global Lax-Friedrichs) at x_{i+1/2}, i = xa-1 .. xb-1 */
@@ -574,11 +776,16 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
     int Q = p->gauss_q;
     double gn[3], gw[3];
     if (gauss_rule(Q, gn, gw)) return -1;
-    /* reconstruct the cells of the rectangle grown by one (corners unused) */
+    /* reconstruct the cells of the rectangle grown by one (corners unused);
+     * in characteristic variables the x-edges take the polynomial built with
+     * the x eigenvectors and the y-edges the one built with the y
+     * eigenvectors, and v-hat (w-hat) comes from the x (y) polynomial */
+    int ch = p->flux == ORC_EULER && p->charwise;
     int rw = xb - xa + 2, rh = yb - ya + 2;
-    double* poly = (double*)malloc(sizeof(double) * (size_t)rw * rh * K * 15);
+    double* poly = (double*)malloc(sizeof(double) * (size_t)rw * rh * K * 15 * 2);
     double* hat = (double*)malloc(sizeof(double) * (size_t)rw * rh * K * 2);
     if (!poly || !hat) { free(poly); free(hat); return -5; }
+    double* polyY = poly + (size_t)rw * rh * K * 15;
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int tj = 0; tj < rh; ++tj) {
         int j = ya - 1 + tj;
@@ -586,24 +793,31 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
             int i = xa - 1 + ti;
             int corner = (ti == 0 || ti == rw - 1) && (tj == 0 || tj == rh - 1);
             if (corner) continue;
+            double q[17 * 4];
             for (int c = 0; c < K; ++c) {
                 const double* ub = ext_at(U, 0, c);
                 const double* vb = ext_at(U, 1, c);
                 const double* wb = ext_at(U, 2, c);
 #define AT(a, ii, jj) (a)[(size_t)(jj) * nxe + (ii)]
-                double q[17] = {
+                double qc[17] = {
                     AT(ub, i - 1, j - 1), AT(ub, i, j - 1), AT(ub, i + 1, j - 1),
                     AT(ub, i - 1, j),     AT(ub, i, j),     AT(ub, i + 1, j),
                     AT(ub, i - 1, j + 1), AT(ub, i, j + 1), AT(ub, i + 1, j + 1),
                     AT(vb, i - 1, j), AT(vb, i + 1, j), AT(vb, i, j - 1), AT(vb, i, j + 1),
                     AT(wb, i - 1, j), AT(wb, i + 1, j), AT(wb, i, j - 1), AT(wb, i, j + 1)};
 #undef AT
-                recon2d_t r;
-                recon_2d(p, q, &r);
+                for (int e = 0; e < 17; ++e) q[e * K + c] = qc[e];
+            }
+            double Cx[4][15], vx[4], wx[4];
+            char_recon_2d(p, q, 0, Cx, vx, wx);
+            double Cy[4][15], vy[4], wy[4];
+            if (ch) char_recon_2d(p, q, 1, Cy, vy, wy);
+            for (int c = 0; c < K; ++c) {
                 size_t o = ((size_t)tj * rw + ti) * K + c;
-                memcpy(poly + o * 15, r.C, sizeof(double) * 15);
-                hat[o * 2 + 0] = r.vhat;
-                hat[o * 2 + 1] = r.what;
+                memcpy(poly + o * 15, Cx[c], sizeof(double) * 15);
+                memcpy(polyY + o * 15, ch ? Cy[c] : Cx[c], sizeof(double) * 15);
+                hat[o * 2 + 0] = vx[c];
+                hat[o * 2 + 1] = ch ? wy[c] : wx[c];
             }
         }
     }
@@ -657,8 +871,8 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
 #pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int e = 0; e < nye_edges; ++e) {
         for (int ti = 1; ti < rw - 1; ++ti) {
-            const double* PB = poly + (((size_t)e * rw + ti) * K) * 15;       /* below */
-            const double* PT = poly + (((size_t)(e + 1) * rw + ti) * K) * 15; /* above */
+            const double* PB = polyY + (((size_t)e * rw + ti) * K) * 15;       /* below */
+            const double* PT = polyY + (((size_t)(e + 1) * rw + ti) * K) * 15; /* above */
             double acc[3][4] = {{0}};
             for (int mu = 0; mu < Q; ++mu) {
                 double UL[4], UR[4], VL[4], VR[4], WL[4], WR[4];
@@ -728,8 +942,8 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
  * of the wrapped cells.)  (i0, j0) is the window origin. */
 static void window_refill(const orc_problem* p, ext_t* e, int i0, int j0, int gx, int gy,
                           int xa, int xb, int ya, int yb) {
-    int tx = p->bc_x == ORC_TRANSMISSIVE;
-    int ty = p->dim == 2 && p->bc_y == ORC_TRANSMISSIVE;
+    int tx = p->bc_x != ORC_PERIODIC;
+    int ty = p->dim == 2 && p->bc_y != ORC_PERIODIC;
     if (!tx && !ty) return;
     for (int v = 0; v < e->nv; ++v)
         for (int c = 0; c < e->K; ++c) {
@@ -737,11 +951,13 @@ static void window_refill(const orc_problem* p, ext_t* e, int i0, int j0, int gx
             for (int jj = ya; jj < yb; ++jj)
                 for (int ii = xa; ii < xb; ++ii) {
                     int gi = i0 + ii - gx, gj = j0 + jj - gy;
-                    int si = tx ? bc_map(gi, p->nx, ORC_TRANSMISSIVE) : gi;
-                    int sj = ty ? bc_map(gj, p->ny, ORC_TRANSMISSIVE) : gj;
+                    int si = tx ? bc_map(gi, p->nx, p->bc_x) : gi;
+                    int sj = ty ? bc_map(gj, p->ny, p->bc_y) : gj;
                     if (si == gi && sj == gj) continue;
+                    double sg = (tx ? bc_sign(p, 0, gi, p->nx, v, c) : 1.0) *
+                                (ty ? bc_sign(p, 1, gj, p->ny, v, c) : 1.0);
                     a[(size_t)jj * e->nxe + ii] =
-                        a[(size_t)(sj - j0 + gy) * e->nxe + (si - i0 + gx)];
+                        sg * a[(size_t)(sj - j0 + gy) * e->nxe + (si - i0 + gx)];
                 }
         }
 }
@@ -806,6 +1022,11 @@ static int check_problem(const orc_problem* p) {
     if (p->dim == 1 && p->ny != 1) return -1;
     if (p->nx < 4 || (p->dim == 2 && p->ny < 4)) return -1;
     if (p->dim == 2 && gauss_rule(p->gauss_q, (double[3]){0}, (double[3]){0})) return -1;
+    if (p->bc_x < ORC_PERIODIC || p->bc_x > ORC_REFLECTIVE) return -1;
+    if (p->dim == 2 && (p->bc_y < ORC_PERIODIC || p->bc_y > ORC_REFLECTIVE)) return -1;
+    if (p->flux != ORC_EULER && (p->bc_x == ORC_REFLECTIVE ||
+                                 (p->dim == 2 && p->bc_y == ORC_REFLECTIVE)))
+        return -1;
     int M = p->dim == 1 ? 2 : 4;
     double s = 0.0;
     for (int m = 0; m <= M; ++m) {

@@ -25,7 +25,7 @@ extern "C" {
 #endif
 
 enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
-enum { ORC_PERIODIC = 0, ORC_TRANSMISSIVE = 1 };
+enum { ORC_PERIODIC = 0, ORC_TRANSMISSIVE = 1, ORC_REFLECTIVE = 2 };
 enum { ORC_W_PAPER = 0, ORC_W_BETA = 1, ORC_W_BETA2 = 2, ORC_W_LINEAR = 3 };
 
 typedef struct {
@@ -33,13 +33,18 @@ typedef struct {
     int flux;              /* ORC_ADVECTION / ORC_BURGERS / ORC_EULER */
     int nx, ny;            /* ny must be 1 in 1D */
     double xlo, xhi, ylo, yhi;
-    int bc_x, bc_y;        /* ORC_PERIODIC / ORC_TRANSMISSIVE */
+    int bc_x, bc_y;        /* ORC_PERIODIC / ORC_TRANSMISSIVE / ORC_REFLECTIVE
+                              (solid wall, Euler only: ghosts mirror the
+                              interior, the normal momentum and the
+                              derivative along the axis change sign) */
     double gas_gamma;      /* ideal gas ratio of specific heats (Euler) */
     double adv[2];         /* advection velocity (a, b) */
     int gauss_q;           /* Gauss points per edge in 2D: 1, 2 or 3 */
     int weights;           /* ORC_W_* */
     double gamma_lin[5];   /* linear weights gamma_0..gamma_M (M=2 in 1D, 4 in 2D) */
     double eps;            /* epsilon of the nonlinear weights */
+    int charwise;          /* Euler: 1 = reconstruct and modify in local
+                              characteristic variables, 0 = per component */
 } orc_problem;
 
 /* Number of conserved components K of the problem. */
@@ -63,6 +68,26 @@ int orc_recon_2d(const orc_problem* p, const double q[17], double* out);
 /* Evaluate a 2D combined polynomial C[15] at local (xi, eta):
  * out = (U, dU/dxi, dU/deta). */
 void orc_poly2d_eval(const double C[15], double xi, double eta, double out[3]);
+
+/* Eigen-decomposition of the Euler flux Jacobian dF/dU in direction dir
+ * (0 = x, 1 = y) at the state U: R (K x K, row-major, columns = right
+ * eigenvectors), L = R^-1 (rows = left eigenvectors), lam = eigenvalues in
+ * the order (v_n - c, v_n, [v_n,] v_n + c).  Returns -1 unless Euler. */
+int orc_euler_eigen(const orc_problem* p, int dir, const double* U, double* R, double* L,
+                    double* lam);
+
+/* Reconstruction of one cell in local characteristic variables (the remark
+ * closing Sec. 2.2): the stencil is projected with the left eigenvectors of
+ * the cell's own average state, every characteristic field goes through the
+ * scalar reconstruction, and the polynomial is mapped back with R.
+ * 1D: ub[3*K] = averages of cells i-1, i, i+1 (cell-major: ub[j*K + c]),
+ *     vb[2*K] = derivative means of cells i-1, i+1; out: C[K][5] then vhat[K].
+ * 2D: q[17*K] = the 17 stencil values of orc_recon_2d, each a K-vector
+ *     (q[s*K + c]); dir picks the x (0) or y (1) eigenvectors; out: C[K][15]
+ *     then vhat[K], what[K].  Returns 0. */
+int orc_recon_char_1d(const orc_problem* p, const double* ub, const double* vb, double dx,
+                      double* out);
+int orc_recon_char_2d(const orc_problem* p, const double* q, int dir, double* out);
 
 /* Physical flux pieces, for the Euler pins.  dir 0 = x, 1 = y.
  * f_out = F(U) (K values); jv_out = (dF/dU) * V (K values). */

@@ -27,7 +27,7 @@ from typing import Callable, List, Optional, Tuple
 import numpy as np
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 GAS_GAMMA = 1.4
 
 
@@ -275,6 +275,74 @@ def _piecewise_average_1d(spec: Spec, cuts, states, k, phi, nq=6):
     st[0, :, 0, :] = ubar
     st[1, :, 0, :] = (right - left) / dx
     return st
+
+
+def piecewise_1d(spec: Spec, cuts, pieces, nq: int = 8) -> np.ndarray:
+    """1D Euler data made of pieces separated by the points `cuts`; piece s is
+    a callable x -> (rho, u, p) (arrays).  Averages are Gauss sums over each
+    piece's part of a cell (exact up to the rule's order on smooth pieces),
+    and the derivative mean is the difference of the face traces taken from
+    inside the cell, divided by dx."""
+    nx, dx = spec.nx, spec.dx
+    edges = np.concatenate([[spec.xlo], np.asarray(cuts, dtype=np.float64), [spec.xhi]])
+    xl = spec.xlo + dx * np.arange(nx)
+    xr = xl + dx
+    gx, gw = _gauss(nq)
+
+    def cons(x, s):
+        rho, u, p = pieces[s](x)
+        return conserved_1d(rho + 0 * x, u + 0 * x, p + 0 * x, spec.gas_gamma)
+
+    ubar = np.zeros((3, nx))
+    for s in range(len(pieces)):
+        a = np.clip(edges[s], xl, xr)
+        b = np.clip(edges[s + 1], xl, xr)
+        length = b - a
+        m = length > 0
+        for xq, wq in zip(gx, gw):
+            ubar[:, m] += (wq * length[m] / dx) * cons(a[m] + xq * length[m], s)
+    seg_r = np.clip(np.searchsorted(edges, xr, side="left") - 1, 0, len(pieces) - 1)
+    seg_l = np.clip(np.searchsorted(edges, xl, side="right") - 1, 0, len(pieces) - 1)
+    right = np.zeros((3, nx))
+    left = np.zeros((3, nx))
+    for s in range(len(pieces)):
+        mr, ml = seg_r == s, seg_l == s
+        right[:, mr] = cons(xr[mr], s)
+        left[:, ml] = cons(xl[ml], s)
+    st = np.zeros(spec.shape())
+    st[0, :, 0, :] = ubar
+    st[1, :, 0, :] = (right - left) / dx
+    return st
+
+
+def lax_1d(nx: int = 100) -> Tuple[Spec, np.ndarray]:
+    """Lax shock tube (Sec. 3.2): [-0.5, 0.5], jump at 0, T = 0.16; the waves
+    stay inside the domain, so the inflow/outflow ends are transmissive."""
+    spec = Spec(dim=1, flux=EULER, nx=nx, xlo=-0.5, xhi=0.5, bc_x=TRANSMISSIVE, t_end=0.16,
+                name=f"lax-1d-{nx}")
+    return spec, piecewise_1d(spec, [0.0], [lambda x: (0.445, 0.698, 3.528),
+                                            lambda x: (0.5, 0.0, 0.571)])
+
+
+def blast_1d(nx: int = 800) -> Tuple[Spec, np.ndarray]:
+    """Interacting blast waves (Sec. 3.2): [0, 1], pressures 1000 / 0.01 /
+    100 with cuts at 0.1 and 0.9, density 1 at rest, solid walls at both
+    ends, T = 0.038."""
+    spec = Spec(dim=1, flux=EULER, nx=nx, xlo=0.0, xhi=1.0, bc_x=REFLECTIVE, t_end=0.038,
+                name=f"blast-1d-{nx}")
+    return spec, piecewise_1d(spec, [0.1, 0.9], [lambda x: (1.0, 0.0, 1000.0),
+                                                 lambda x: (1.0, 0.0, 0.01),
+                                                 lambda x: (1.0, 0.0, 100.0)])
+
+
+def shu_osher_1d(nx: int = 400) -> Tuple[Spec, np.ndarray]:
+    """Shu-Osher shock/entropy-wave problem (Sec. 3.2): [-5, 5], shock at
+    x = -4, density 1 + 0.2 sin(5 pi x) ahead of it, outflow ends, T = 1.8."""
+    spec = Spec(dim=1, flux=EULER, nx=nx, xlo=-5.0, xhi=5.0, bc_x=TRANSMISSIVE, t_end=1.8,
+                name=f"shu-osher-1d-{nx}")
+    return spec, piecewise_1d(spec, [-4.0], [
+        lambda x: (3.857143, 2.629369, 10.33333),
+        lambda x: (1.0 + 0.2 * np.sin(5.0 * np.pi * x), 0.0, 1.0)])
 
 
 def batched_1d(seed: int = 1, nprob: int = 4096, nmin: int = 256, nmax: int = 8192,
