@@ -212,9 +212,20 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
         const int li = bc_map(gi, nx, bcx);         // column it reads
         const bool out_col = lane >= 2 && lane < 62 && gi < nx;
 
-        const TU* Uu = (const TU*)a.in.u + P_.off_u + c * plane;
-        const TD* Uv = (const TD*)a.in.d + P_.off_d + c * plane;
-        const TD* Uw = (const TD*)a.in.d + P_.off_d + (K + c) * plane;
+        // Every pointer of the march is formed here, once per tile: fields of
+        // the problem table read inside the row loop would be reloaded after
+        // each store (possible aliasing) and waited for with every load in
+        // flight, the row-ahead prefetch included.
+        const int64_t off_u = P_.off_u, off_d = P_.off_d;
+        const TU* Uu = (const TU*)a.in.u + off_u + c * plane;
+        const TD* Uv = (const TD*)a.in.d + off_d + c * plane;
+        const TD* Uw = (const TD*)a.in.d + off_d + (K + c) * plane;
+        const TU* Un = (const TU*)a.un + off_u + c * plane;     // stages 2, 3: U^n
+        TD* Hv = (TD*)a.h + off_d + c * plane;                  // saved derivatives
+        TD* Hw = (TD*)a.h + off_d + (K + c) * plane;
+        TU* Ou = (TU*)a.out.u + off_u + c * plane;
+        TD* Ov = (TD*)a.out.d + off_d + c * plane;
+        TD* Ow = (TD*)a.out.d + off_d + (K + c) * plane;
 
         auto row_ptr = [&](int j) { return (int64_t)bc_map(j, ny, bcy) * nx + li; };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
@@ -270,10 +281,13 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
             T hvr = 0, hwr = 0;
             const bool emit = r > j0 && out_col;   // row r-1 is an output row
             const int64_t oo = (int64_t)(r - 1) * nx + gi;  // output row r-1 (in range if emit)
-            if (emit && (mode == MODE_S2 || mode == MODE_S3)) {
-                unr = (TA)((const TU*)a.un)[P_.off_u + c * plane + oo];
-                hvr = (T)((const TD*)a.h)[P_.off_d + c * plane + oo];
-                hwr = (T)((const TD*)a.h)[P_.off_d + (K + c) * plane + oo];
+            if (mode == MODE_S2 || mode == MODE_S3) {
+                // unconditional (lanes without output read element 0) so that
+                // the loads stay in flight until the epilogue uses them
+                const int64_t ol = emit ? oo : 0;
+                unr = (TA)Un[ol];
+                hvr = (T)Hv[ol];
+                hwr = (T)Hw[ol];
             }
 
             // ---- R: reconstruct cell (gi, r), component c -------------------
@@ -403,18 +417,14 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                             a.Uh_out[K * plane + ob] = (double)hat_prev[0];
                             a.Uh_out[2 * K * plane + ob] = (double)hat_prev[1];
                         } else {
-                            TU* Ou = (TU*)a.out.u + P_.off_u + c * plane;
-                            TD* Ov = (TD*)a.out.d + P_.off_d + c * plane;
-                            TD* Ow = (TD*)a.out.d + P_.off_d + (K + c) * plane;
                             const TA dta = (TA)dt;
                             const T dtt = (T)dt;
                             if (mode == MODE_S1) {
                                 Ou[oo] = (TU)(ucur + dta * Lu);
                                 Ov[oo] = (TD)(hat_prev[0] + dtt * Lv);
                                 Ow[oo] = (TD)(hat_prev[1] + dtt * Lw);
-                                TD* H = (TD*)a.h + P_.off_d;
-                                H[c * plane + oo] = (TD)hat_prev[0];
-                                H[(K + c) * plane + oo] = (TD)hat_prev[1];
+                                Hv[oo] = (TD)hat_prev[0];
+                                Hw[oo] = (TD)hat_prev[1];
                             } else if (mode == MODE_S2) {
                                 Ou[oo] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
                                 Ov[oo] = (TD)((T)0.75 * hvr + (T)0.25 * (hat_prev[0] + dtt * Lv));
