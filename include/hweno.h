@@ -50,9 +50,13 @@ enum {
  * linear advection f = a u, g = b u). */
 enum { HWENO_ADVECTION = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 };
 
-/* Boundary treatment per axis: periodic wrap, or transmissive (every unknown
- * of the ghost cells copied from the nearest interior cell). */
-enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1 };
+/* Boundary treatment per axis: periodic wrap; transmissive (every unknown
+ * of the ghost cells copied from the nearest interior cell; the inflow and
+ * outflow ends of Sec. 3.2's tubes); reflective, a solid wall (Euler only:
+ * the ghost cells hold the mirror image of the interior, with the normal
+ * momentum and the derivative means along the wall normal of the other
+ * quantities negated; the blast-wave problem of Sec. 3.2). */
+enum { HWENO_PERIODIC = 0, HWENO_TRANSMISSIVE = 1, HWENO_REFLECTIVE = 2 };
 
 /* Arithmetic of the path:
  *   F64       everything in double precision;
@@ -77,7 +81,7 @@ typedef struct {
     int32_t flux;         /* HWENO_ADVECTION / HWENO_BURGERS / HWENO_EULER */
     int32_t nx, ny;       /* cells; nx >= 4, ny >= 4 in 2D, ny = 1 in 1D    */
     double xlo, xhi, ylo, yhi; /* domain [xlo,xhi] x [ylo,yhi]             */
-    int32_t bc_x, bc_y;   /* HWENO_PERIODIC / HWENO_TRANSMISSIVE           */
+    int32_t bc_x, bc_y;   /* HWENO_PERIODIC / _TRANSMISSIVE / _REFLECTIVE  */
     double gas_gamma;     /* ratio of specific heats (Euler), e.g. 1.4      */
     double adv[2];        /* advection velocity (a, b)                      */
     double t_end;         /* final time used by hweno_run_to_time           */
@@ -95,11 +99,17 @@ typedef struct {
     double dt_exponent;   /* 1: dt = cfl*dx/alpha (1D), cfl/(ax/dx+ay/dy)
                              (2D); e != 1 uses dx^e, dy^e (5/3 for the
                              accuracy runs of Sec. 3.1)                    */
+    int32_t characteristic; /* Euler only: 1 = reconstruction and derivative
+                             modification in the local characteristic
+                             variables of each cell's own average (remark
+                             closing Sec. 2.2), 0 = per conserved
+                             component; scalar laws ignore it             */
+    int32_t reserved_;    /* zero                                           */
 } hweno_config;
 
 /* Fills cfg with the paper's settings for dimension dim: gamma = 1/400 per
  * linear polynomial and the rest on p0 (Sec. 3), eps = 1e-8, CFL 0.6, Q = 3,
- * W_BETA, F64, dt_exponent 1. */
+ * W_BETA, F64, dt_exponent 1, component-wise reconstruction. */
 void hweno_default_config(int32_t dim, hweno_config* cfg);
 
 /* Bytes of device memory hweno_create needs for these problems, so that a

@@ -112,9 +112,12 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
             return fail(h, HWENO_ERR_ARG, "problem %d: too many cells", p);
         if (!(q.xhi > q.xlo) || (dim == 2 && !(q.yhi > q.ylo)))
             return fail(h, HWENO_ERR_ARG, "problem %d: empty domain", p);
-        if ((q.bc_x != HWENO_PERIODIC && q.bc_x != HWENO_TRANSMISSIVE) ||
-            (dim == 2 && q.bc_y != HWENO_PERIODIC && q.bc_y != HWENO_TRANSMISSIVE))
+        if (q.bc_x < HWENO_PERIODIC || q.bc_x > HWENO_REFLECTIVE ||
+            (dim == 2 && (q.bc_y < HWENO_PERIODIC || q.bc_y > HWENO_REFLECTIVE)))
             return fail(h, HWENO_ERR_ARG, "problem %d: unknown boundary type", p);
+        if (flux != HWENO_EULER &&
+            (q.bc_x == HWENO_REFLECTIVE || (dim == 2 && q.bc_y == HWENO_REFLECTIVE)))
+            return fail(h, HWENO_ERR_ARG, "problem %d: reflective walls need the Euler flux", p);
         if (flux == HWENO_EULER && !(q.gas_gamma > 1.0))
             return fail(h, HWENO_ERR_ARG, "problem %d: gas_gamma must exceed 1", p);
         if (q.gas_gamma != probs[0].gas_gamma || q.adv[0] != probs[0].adv[0] ||
@@ -138,6 +141,10 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
     if (!(cfg->eps > 0.0)) return fail(h, HWENO_ERR_ARG, "eps must be positive");
     if (!(cfg->cfl > 0.0)) return fail(h, HWENO_ERR_ARG, "cfl must be positive");
     if (!(cfg->dt_exponent > 0.0)) return fail(h, HWENO_ERR_ARG, "dt_exponent must be positive");
+    if (cfg->characteristic != 0 && cfg->characteristic != 1)
+        return fail(h, HWENO_ERR_ARG, "characteristic must be 0 or 1");
+    if (cfg->characteristic && dim == 2 && flux == HWENO_EULER)
+        return fail(h, HWENO_ERR_ARG, "characteristic reconstruction is available in 1D only");
     return HWENO_OK;
 }
 
@@ -314,6 +321,7 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     h->sch.adv[1] = probs[0].adv[1];
     h->sch.weights = cfg->weights;
     h->sch.Q = cfg->gauss_q;
+    h->sch.charwise = cfg->characteristic && h->flux == F_EULER;
 
     // problem table
     h->h_probs.resize(nprob);

@@ -20,14 +20,34 @@ template <> struct PrecT<P_ACC64> { using TU = double; using TD = float; using T
 template <> struct PrecT<P_KAHAN> { using TU = ffs; using TD = float; using T = float; using TA = ff; };
 
 // Ghost cells as index maps: periodic wraps, transmissive clamps to the
-// nearest interior cell (every unknown of a ghost cell is that cell's).
+// nearest interior cell (every unknown of a ghost cell is that cell's),
+// reflective mirrors (with the signs of wall_mirrored below).
 __device__ __forceinline__ int bc_map(int i, int n, int bc) {
     if (bc == BC_PERIODIC) {
         int r = i % n;
         return r < 0 ? r + n : r;
     }
+    if (bc == BC_REFLECTIVE) {   // mirror images across both walls (period 2n)
+        if (i >= 0 && i < n) return i;
+        int r = i % (2 * n);
+        if (r < 0) r += 2 * n;
+        return r < n ? r : 2 * n - 1 - r;
+    }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
+
+// True where index i lies in a mirror image of the domain across a solid
+// wall (an odd number of reflections): there the normal momentum is odd and
+// every other conserved quantity even, and the derivative mean along the
+// wall normal has the opposite parity of its quantity.
+__device__ __forceinline__ bool wall_mirrored(int i, int n, int bc) {
+    if (bc != BC_REFLECTIVE || (i >= 0 && i < n)) return false;
+    int r = i % (2 * n);
+    if (r < 0) r += 2 * n;
+    return r >= n;
+}
+
+template <class V> __device__ __forceinline__ V neg_if(V x, bool neg) { return neg ? -x : x; }
 
 __device__ __forceinline__ double as_double(uint64_t b) { return __longlong_as_double((long long)b); }
 
@@ -226,6 +246,69 @@ __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, doubl
         }
     }
 }
+
+// ------------------------------------------- characteristic variables ---
+//
+// Eigenvectors of the Euler flux Jacobian at a cell's own average, for the
+// reconstruction in local characteristic variables (remark closing Sec.
+// 2.2).  U = (rho, m_n, [m_t,] E) with m_n the momentum along the direction
+// and m_t across it; columns of R (rows of L = R^-1) belong to the
+// eigenvalues v_n - c, v_n, [v_n (shear),] v_n + c.
+template <class T, int K> struct Eigen {
+    T R[K][K], L[K][K];
+    __device__ __forceinline__ Eigen(const T* U, T gm1) {
+        const T ir = rcp(U[0]);
+        const T vn = U[1] * ir;
+        const T vt = K == 4 ? U[2] * ir : (T)0;
+        const T hq2 = (T)0.5 * (vn * vn + vt * vt);
+        const T p = gm1 * (U[K - 1] - U[0] * hq2);
+        const T c2 = (gm1 + (T)1) * p * ir;
+        const T c = sqrt(c2);
+        const T ic = rcp(c);
+        const T H = (U[K - 1] + p) * ir;
+        const T b1 = gm1 * ic * ic, b2 = b1 * hq2;
+        const T ec = (T)0.5 * ic;
+        const T hb1 = (T)0.5 * b1;
+        if constexpr (K == 3) {
+            R[0][0] = 1;          R[0][1] = 1;   R[0][2] = 1;
+            R[1][0] = vn - c;     R[1][1] = vn;  R[1][2] = vn + c;
+            R[2][0] = H - vn * c; R[2][1] = hq2; R[2][2] = H + vn * c;
+            L[0][0] = (T)0.5 * b2 + vn * ec; L[0][1] = -(hb1 * vn + ec); L[0][2] = hb1;
+            L[1][0] = (T)1 - b2;             L[1][1] = b1 * vn;          L[1][2] = -b1;
+            L[2][0] = (T)0.5 * b2 - vn * ec; L[2][1] = ec - hb1 * vn;    L[2][2] = hb1;
+        } else {
+            R[0][0] = 1;          R[0][1] = 1;   R[0][2] = 0;  R[0][3] = 1;
+            R[1][0] = vn - c;     R[1][1] = vn;  R[1][2] = 0;  R[1][3] = vn + c;
+            R[2][0] = vt;         R[2][1] = vt;  R[2][2] = 1;  R[2][3] = vt;
+            R[3][0] = H - vn * c; R[3][1] = hq2; R[3][2] = vt; R[3][3] = H + vn * c;
+            L[0][0] = (T)0.5 * b2 + vn * ec; L[0][1] = -(hb1 * vn + ec);
+            L[0][2] = -hb1 * vt;             L[0][3] = hb1;
+            L[1][0] = (T)1 - b2; L[1][1] = b1 * vn; L[1][2] = b1 * vt; L[1][3] = -b1;
+            L[2][0] = -vt;       L[2][1] = 0;       L[2][2] = 1;       L[2][3] = 0;
+            L[3][0] = (T)0.5 * b2 - vn * ec; L[3][1] = ec - hb1 * vn;
+            L[3][2] = -hb1 * vt;             L[3][3] = hb1;
+        }
+    }
+    // w = L x and x = R w (vectors in the (rho, m_n, [m_t,] E) order)
+    __device__ __forceinline__ void left(const T* x, T* w) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            T a = 0;
+#pragma unroll
+            for (int c = 0; c < K; ++c) a += L[k][c] * x[c];
+            w[k] = a;
+        }
+    }
+    __device__ __forceinline__ void right(const T* w, T* x) const {
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            T a = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) a += R[c][k] * w[k];
+            x[c] = a;
+        }
+    }
+};
 
 // ----------------------------------------------------- nonlinear weights ---
 //

@@ -19,6 +19,13 @@ struct ffs {
     __host__ __device__ explicit operator float() const { return hi + lo; }
 };
 
+__host__ __device__ inline ffs operator-(ffs a) {
+    ffs r;
+    r.hi = -a.hi;
+    r.lo = -a.lo;
+    return r;
+}
+
 // Difference of two stored averages, rounded once to float: the hi parts of
 // neighbouring averages are close, so hi - hi is exact (Sterbenz) or nearly.
 __device__ __forceinline__ float operator-(ffs a, ffs b) { return (a.hi - b.hi) + (a.lo - b.lo); }

@@ -1,5 +1,6 @@
 // Fused 1D HWENO stage kernel: reconstruction (Sec. 2.1 Steps 1-3,
-// Appendix A), interface values, global Lax-Friedrichs fluxes for f and h,
+// Appendix A; for the Euler equations optionally in local characteristic
+// variables, CH), interface values, global Lax-Friedrichs fluxes for f and h,
 // the residual of eq. semi-discrete-scheme and the SSP-RK3 stage with the
 // modified derivative (Sec. 2.1 Step 4).
 //
@@ -14,7 +15,7 @@
 
 namespace hweno {
 
-template <int P, int K, int FLUX, int mode>
+template <int P, int K, int FLUX, int mode, bool CH>
 __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
@@ -46,27 +47,45 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
         const T alpha = (T)as_double(P_.ax_bits);
         const double dt = P_.dt;
         const int c0 = tile.c0;
+        // problem-table fields are copied before any store: read after one,
+        // they would be reloaded (possible aliasing) and waited for
+        const int64_t off_u = P_.off_u, off_d = P_.off_d;
 
         for (int k = tid; k < NL; k += 256) {
             const int src = bc_map(c0 - 2 + k, nx, bcx);
+            const bool mir = FLUX == F_EULER && wall_mirrored(c0 - 2 + k, nx, bcx);
 #pragma unroll
             for (int c = 0; c < K; ++c) {
-                su[c][k] = ((const TU*)a.in.u)[P_.off_u + (int64_t)c * nx + src];
-                sv[c][k] = ((const TD*)a.in.d)[P_.off_d + (int64_t)c * nx + src];
+                // behind a wall: momentum odd, other averages even, and the
+                // derivative means of the opposite parity
+                su[c][k] = neg_if(((const TU*)a.in.u)[off_u + (int64_t)c * nx + src], mir && c == 1);
+                sv[c][k] = neg_if(((const TD*)a.in.d)[off_d + (int64_t)c * nx + src], mir && c != 1);
+            }
+        }
+        // stages 2 and 3: U^n and the saved derivatives of the output cell,
+        // loaded now (lanes without output read element 0) so that they arrive
+        // while the cell is reconstructed and the fluxes are formed
+        const int gi = c0 - 1 + tid;
+        const bool emit = tid >= 1 && tid <= TILE1D_OUT && gi < nx;
+        TA unr[K];
+        T hnr[K];
+        if (mode == MODE_S2 || mode == MODE_S3) {
+            const int gl = emit ? gi : 0;
+#pragma unroll
+            for (int c = 0; c < K; ++c) {
+                unr[c] = (TA)((const TU*)a.un)[off_u + (int64_t)c * nx + gl];
+                hnr[c] = (T)((const TD*)a.h)[off_d + (int64_t)c * nx + gl];
             }
         }
         __syncthreads();
 
         // ---- reconstruct local cell tid (global c0 - 1 + tid) ---------------
-        T vhat[K];
-#pragma unroll
-        for (int c = 0; c < K; ++c) {
-            const TU uc = su[c][tid + 1];
-            const T dm = (T)(su[c][tid] - uc);        // u_{i-1} - u_i
-            const T dp = (T)(su[c][tid + 2] - uc);    // u_{i+1} - u_i
-            const T dvm = dx * (T)sv[c][tid];         // dx * v_{i-1}
-            const T dvp = dx * (T)sv[c][tid + 2];     // dx * v_{i+1}
-            // Appendix A with the centre average subtracted (constant relative)
+        // Per field: the differences of the neighbours' averages from the
+        // cell's (dm, dp) and dx times their derivative means (dvm, dvp) give
+        // the Appendix A quartic (centre average subtracted), the two linear
+        // polynomials, the weights, and the combined polynomial's even and
+        // odd parts at the faces (E, O) and of its derivative (De, Do).
+        auto recon_field = [&](T dm, T dp, T dvm, T dvp, T& E, T& O, T& De, T& Do) {
             T c0v[5];
             c0v[0] = (T)(-47.0 / 480.0) * (dm + dp) + (T)(9.0 / 320.0) * (dvp - dvm);
             c0v[1] = (T)(13.0 / 16.0) * (dp - dm) - (T)(5.0 / 16.0) * (dvm + dvp);
@@ -86,15 +105,53 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
 #pragma unroll
             for (int l = 0; l < 5; ++l) C[l] = a0 * c0v[l];
             C[1] += b2 * dp - b1 * dm;   // slopes of p1 (-dm) and p2 (dp)
-            const T E = C[0] + (T)0.25 * C[2] + (T)0.0625 * C[4];
-            const T O = (T)0.5 * C[1] + (T)0.125 * C[3];
-            const T De = C[1] + (T)0.75 * C[3], Do = C[2] + (T)0.5 * C[4];
-            const T ucT = (T)uc;
-            sR[c][tid] = ucT + (E + O);
-            sL[c][tid] = ucT + (E - O);
-            sR[K + c][tid] = (De + Do) * inv_dx;
-            sL[K + c][tid] = (De - Do) * inv_dx;
-            vhat[c] = (T)2 * O * inv_dx;   // (u(x+1/2) - u(x-1/2)) / dx
+            E = C[0] + (T)0.25 * C[2] + (T)0.0625 * C[4];
+            O = (T)0.5 * C[1] + (T)0.125 * C[3];
+            De = C[1] + (T)0.75 * C[3];
+            Do = C[2] + (T)0.5 * C[4];
+        };
+        T dm[K], dp[K], dvm[K], dvp[K], E[K], O[K], De[K], Do[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const TU uc = su[c][tid + 1];
+            dm[c] = (T)(su[c][tid] - uc);        // u_{i-1} - u_i
+            dp[c] = (T)(su[c][tid + 2] - uc);    // u_{i+1} - u_i
+            dvm[c] = dx * (T)sv[c][tid];         // dx * v_{i-1}
+            dvp[c] = dx * (T)sv[c][tid + 2];     // dx * v_{i+1}
+        }
+        if constexpr (CH) {
+            // local characteristic variables of the cell's own average: the
+            // reconstruction is linear in the stencil except for the weights,
+            // so the differences project directly and the face values map
+            // back with R
+            T Uc[K];
+#pragma unroll
+            for (int c = 0; c < K; ++c) Uc[c] = (T)su[c][tid + 1];
+            const Eigen<T, K> ev(Uc, (T)(sch.gas_gamma - 1.0));
+            T wm[K], wp[K], wvm[K], wvp[K], e[K], o[K], de[K], dd[K];
+            ev.left(dm, wm);
+            ev.left(dp, wp);
+            ev.left(dvm, wvm);
+            ev.left(dvp, wvp);
+#pragma unroll
+            for (int k = 0; k < K; ++k) recon_field(wm[k], wp[k], wvm[k], wvp[k], e[k], o[k], de[k], dd[k]);
+            ev.right(e, E);
+            ev.right(o, O);
+            ev.right(de, De);
+            ev.right(dd, Do);
+        } else {
+#pragma unroll
+            for (int c = 0; c < K; ++c) recon_field(dm[c], dp[c], dvm[c], dvp[c], E[c], O[c], De[c], Do[c]);
+        }
+        T vhat[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const T ucT = (T)su[c][tid + 1];
+            sR[c][tid] = ucT + (E[c] + O[c]);
+            sL[c][tid] = ucT + (E[c] - O[c]);
+            sR[K + c][tid] = (De[c] + Do[c]) * inv_dx;
+            sL[K + c][tid] = (De[c] - Do[c]) * inv_dx;
+            vhat[c] = (T)2 * O[c] * inv_dx;   // (u(x+1/2) - u(x-1/2)) / dx
         }
         __syncthreads();
 
@@ -118,8 +175,6 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
         __syncthreads();
 
         // ---- residual and RK stage of local cell tid -----------------------
-        const int gi = c0 - 1 + tid;
-        const bool emit = tid >= 1 && tid <= TILE1D_OUT && gi < nx;
         double unew[K];
         if (emit) {
 #pragma unroll
@@ -127,8 +182,8 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
                 const TA Lu = -((TA)sF[c][tid] - (TA)sF[c][tid - 1]) * inv_dx_a;
                 const T Lv = -(sF[K + c][tid] - sF[K + c][tid - 1]) * inv_dx;
                 const TA ucur = (TA)su[c][tid + 1];
-                const int64_t ou = P_.off_u + (int64_t)c * nx + gi;
-                const int64_t od = P_.off_d + (int64_t)c * nx + gi;
+                const int64_t ou = off_u + (int64_t)c * nx + gi;
+                const int64_t od = off_d + (int64_t)c * nx + gi;
                 if (mode == MODE_RHS) {
                     const int64_t ob = (int64_t)c * nx + gi;
                     a.L_out[ob] = (double)Lu;
@@ -145,13 +200,12 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
                         Ov[od] = (TD)(vhat[c] + dtt * Lv);
                         ((TD*)a.h)[od] = (TD)vhat[c];
                     } else {
-                        const TA unr = (TA)((const TU*)a.un)[ou];
-                        const T hn = (T)((const TD*)a.h)[od];
+                        const T hn = hnr[c];
                         if (mode == MODE_S2) {
-                            Ou[ou] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
+                            Ou[ou] = (TU)((TA)0.75 * unr[c] + (TA)0.25 * (ucur + dta * Lu));
                             Ov[od] = (TD)((T)0.75 * hn + (T)0.25 * (vhat[c] + dtt * Lv));
                         } else {
-                            const TU nu = (TU)((TA)(1.0 / 3.0) * unr + (TA)(2.0 / 3.0) * (ucur + dta * Lu));
+                            const TU nu = (TU)((TA)(1.0 / 3.0) * unr[c] + (TA)(2.0 / 3.0) * (ucur + dta * Lu));
                             Ou[ou] = nu;
                             unew[c] = (double)nu;
                             Ov[od] = (TD)((T)(1.0 / 3.0) * hn + (T)(2.0 / 3.0) * (vhat[c] + dtt * Lv));

@@ -228,6 +228,20 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
         TD* Ow = (TD*)a.out.d + off_d + (K + c) * plane;
 
         auto row_ptr = [&](int j) { return (int64_t)bc_map(j, ny, bcy) * nx + li; };
+        // Solid walls: in a mirror image across x the x momentum (component
+        // 1) is odd and the other averages even, and v-bar has the opposite
+        // parity of its quantity; across y likewise with component 2 and
+        // w-bar.  Signs of this lane's column, and of a row.
+        const bool mx = FLUX == F_EULER && wall_mirrored(gi, nx, bcx);
+        const bool nux = mx && c == 1, nvx = mx && c != 1, nwx = mx && c == 1;
+        auto load_row = [&](int j, TU& u, TD& v, TD& w) {
+            const int64_t o = row_ptr(j);
+            const bool my = FLUX == F_EULER && wall_mirrored(j, ny, bcy);
+            const bool nuy = my && c == 2, nvy = my && c == 2, nwy = my && c != 2;
+            u = neg_if(Uu[o], nux != nuy);
+            v = neg_if(Uv[o], nvx != nvy);
+            w = neg_if(Uw[o], nwx != nwy);
+        };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
 
         // Stage 3 also gathers the wave speeds of the state it writes (for the
@@ -258,14 +272,9 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
 
         TU um, u0, up, un_;
         TD vm, v0, vp, vn_, wm, w0, wp, wn_;
-        {
-            int64_t o = row_ptr(j0 - 2);
-            um = Uu[o]; vm = Uv[o]; wm = Uw[o];
-            o = row_ptr(j0 - 1);
-            u0 = Uu[o]; v0 = Uv[o]; w0 = Uw[o];
-            o = row_ptr(j0);
-            up = Uu[o]; vp = Uv[o]; wp = Uw[o];
-        }
+        load_row(j0 - 2, um, vm, wm);
+        load_row(j0 - 1, u0, v0, w0);
+        load_row(j0, up, vp, wp);
         T ytop[Q][3];            // top-face values of the previous row (this lane, comp)
         TA xd_prev[3] = {0, 0, 0};
         TA gy_prev[3] = {0, 0, 0};
@@ -273,10 +282,7 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
 
         for (int r = j0 - 1; r <= jend; ++r) {
             // prefetch the row two above and the RK inputs of the output row
-            {
-                const int64_t o = row_ptr(r + 2);
-                un_ = Uu[o]; vn_ = Uv[o]; wn_ = Uw[o];
-            }
+            load_row(r + 2, un_, vn_, wn_);
             TA unr = 0;
             T hvr = 0, hwr = 0;
             const bool emit = r > j0 && out_col;   // row r-1 is an output row

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("HWENO_LIB", os.path.join(PKG, "libhweno.so"))
 
 OK, ERR_ARG, ERR_NONFINITE, ERR_HIP, ERR_STATE, ERR_OOM = 0, -1, -2, -3, -4, -5
 ADVECTION, BURGERS, EULER = 0, 1, 2
-PERIODIC, TRANSMISSIVE = 0, 1
+PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 F64, F32, F32_ACC64, F32_KAHAN = 0, 1, 2, 3
 W_PAPER, W_BETA, W_BETA2, W_LINEAR = 0, 1, 2, 3
 
@@ -34,7 +34,8 @@ class hweno_problem(C.Structure):
 class hweno_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gauss_q", C.c_int32), ("weights", C.c_int32),
                 ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("cfl", C.c_double),
-                ("dt_exponent", C.c_double)]
+                ("dt_exponent", C.c_double), ("characteristic", C.c_int32),
+                ("reserved_", C.c_int32)]
 
 
 class hweno_tuning(C.Structure):

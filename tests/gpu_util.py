@@ -11,7 +11,7 @@ def oproblem(spec, cfg):
                      xhi=spec.xhi, ylo=spec.ylo, yhi=spec.yhi, bc_x=spec.bc_x, bc_y=spec.bc_y,
                      gas_gamma=spec.gas_gamma, adv=tuple(spec.adv), gauss_q=cfg.gauss_q,
                      weights=cfg.weights, gamma_lin=tuple(cfg.gamma_lin)[:3 if spec.dim == 1 else 5],
-                     eps=cfg.eps)
+                     eps=cfg.eps, charwise=int(cfg.characteristic))
 
 
 def plane_rel(gpu, ref):
@@ -68,3 +68,38 @@ def rhs_scales(spec, st, ax, ay):
     alpha_y/dy) at which the scheme moves it."""
     rate = ax / spec.dx + (ay / spec.dy if spec.dim == 2 else 0.0)
     return natural_scales(spec, st) * max(rate, 1e-300)
+
+
+def scaled_err_planes(gpu, ref, scales):
+    """scaled_err per (var, comp) plane (array of shape (nvar, K))"""
+    g = np.asarray(gpu, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    ax = tuple(range(2, r.ndim))
+    d = np.abs(g - r).max(axis=ax)
+    return d / np.maximum(scales, np.abs(r).max(axis=ax))
+
+
+def oracle_sensitivity(fn, st, scales, rel=1e-15, samples=2, seed=0):
+    """Per (var, comp) plane, the largest scaled distance between fn(st) and
+    fn of st perturbed by a relative `rel` (normal noise), over a few draws:
+    how far rounding-level input differences move the oracle's own result.
+    Where the scheme amplifies them (strong jumps; in characteristic
+    variables the projection with |L| |R| >> 1 at low sound speed), a GPU
+    result that differs from the oracle only by rounding is held, plane by
+    plane, to a bar of a few times this distance."""
+    rng = np.random.default_rng(seed)
+    ref = fn(st)
+    worst = None
+    for _ in range(samples):
+        out = fn(st * (1.0 + rel * rng.standard_normal(st.shape)))
+        e = scaled_err_planes(out, ref, scales)
+        worst = e if worst is None else np.maximum(worst, e)
+    return worst
+
+
+def within_conditioning(gpu, ref, scales, sens, floor):
+    """True if every plane's scaled error is at most max(floor, 10 * its
+    oracle sensitivity); returns (ok, errors, bars) for the message"""
+    err = scaled_err_planes(gpu, ref, scales)
+    bar = np.maximum(floor, 10.0 * sens)
+    return bool(np.all(err <= bar)), err, bar
