@@ -20,7 +20,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 SOURCES = ["stage2d_f64.hip", "stage2d_f32.hip", "stage2d_acc64.hip", "stage2d_kahan.hip",
-           "stage2d.hip",
+           "stage2d_char.hip", "stage2d.hip",
            "stage1d.hip", "control.hip", "api.cpp"]
 
 

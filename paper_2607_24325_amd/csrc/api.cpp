@@ -143,8 +143,6 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
     if (!(cfg->dt_exponent > 0.0)) return fail(h, HWENO_ERR_ARG, "dt_exponent must be positive");
     if (cfg->characteristic != 0 && cfg->characteristic != 1)
         return fail(h, HWENO_ERR_ARG, "characteristic must be 0 or 1");
-    if (cfg->characteristic && dim == 2 && flux == HWENO_EULER)
-        return fail(h, HWENO_ERR_ARG, "characteristic reconstruction is available in 1D only");
     return HWENO_OK;
 }
 

@@ -185,9 +185,12 @@ template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
 // ------------------------------------------------------------ wave speeds --
 //
 // |f'(u)| and |g'(u)| at the cell average U (Euler: |velocity| + sound
-// speed), in double precision with no contraction, so that every kernel
-// that evaluates it produces the same bits; returns false if U is not
-// finite or (Euler) rho <= 0 or p <= 0.
+// speed), in double precision with no contraction and IEEE divisions, so
+// that every kernel that evaluates it produces the same bits, and the same
+// bits as a plain evaluation of the definition (time steps then agree
+// exactly with a reference run, also along trajectories that end in a
+// non-admissible state); returns false if U is not finite or (Euler)
+// rho <= 0 or p <= 0.
 template <int FLUX, int DIM, int K>
 __device__ __forceinline__ bool wave_speed(const double* u, const Scheme& sch, double& sx,
                                            double& sy) {
@@ -230,21 +233,28 @@ __device__ __forceinline__ long long wave_min_ll(long long v) {
     return v;
 }
 
-// Folds one wave's speeds and first bad cell into the problem's slots for
-// the state being written (lane 0 issues the atomics).
+// Folds reduced speeds and a first bad cell into the problem's slots for the
+// state being written (one lane calls this).  Speeds are non-negative, so
+// their bit patterns order as unsigned integers.
+__device__ __forceinline__ void publish_reduced(ProbDev& P, double mx, double my,
+                                                long long bad) {
+    atomicMax((unsigned long long*)&P.ax_next, (unsigned long long)__double_as_longlong(mx));
+    if (my > 0.0)
+        atomicMax((unsigned long long*)&P.ay_next, (unsigned long long)__double_as_longlong(my));
+    if (bad != LLONG_MAX) {
+        atomicMin((long long*)&P.bad_cell, bad);
+        atomicOr(&P.err, 1);
+    }
+}
+
+// Wave-level version: every lane brings its values, lane 0 publishes.  The
+// bad-cell minimum is only formed when some lane has one.
 __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, double my,
                                                     long long bad) {
     mx = wave_max_d(mx);
     my = wave_max_d(my);
-    bad = wave_min_ll(bad);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax((unsigned long long*)&P.ax_next, (unsigned long long)__double_as_longlong(mx));
-        atomicMax((unsigned long long*)&P.ay_next, (unsigned long long)__double_as_longlong(my));
-        if (bad != LLONG_MAX) {
-            atomicMin((long long*)&P.bad_cell, bad);
-            atomicOr(&P.err, 1);
-        }
-    }
+    if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
+    if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad);
 }
 
 // ------------------------------------------- characteristic variables ---

@@ -27,7 +27,7 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     __shared__ T sR[2 * K][256];         // (u, u_x) at x_{i+1/2} from cell i
     __shared__ T sL[2 * K][256];         // (u, u_x) at x_{i-1/2} from cell i
     __shared__ T sF[2 * K][256];         // (f-hat, h-hat) at the right interface of cell t
-    __shared__ double s_mx[4], s_my[4];  // stage 3: per-wave maxima of the wave speeds
+    __shared__ double s_mx[4];           // stage 3: per-wave maxima of the wave speeds
     __shared__ long long s_bad[4];
 
     const int tid = threadIdx.x;
@@ -215,34 +215,34 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
             }
         }
         if (mode == MODE_S3) {
-            // wave speeds of the state being written, for the next step:
-            // reduced over the wave here and over the workgroup below
-            double mx = 0.0, my = 0.0;
+            // largest x wave speed of the state being written (the 1D time
+            // step uses no other), for the next step: reduced over the wave
+            // here and over the workgroup below; the first non-admissible
+            // cell is reduced only where there is one
+            double mx = 0.0;
             long long bad = LLONG_MAX;
             if (emit) {
                 double sx, sy;
-                if (wave_speed<FLUX, 1, K>(unew, sch, sx, sy)) {
-                    mx = sx;
-                    my = sy;
-                } else {
-                    bad = gi;
-                }
+                if (wave_speed<FLUX, 1, K>(unew, sch, sx, sy)) mx = sx;
+                else bad = gi;
             }
             mx = wave_max_d(mx);
-            my = wave_max_d(my);
-            bad = wave_min_ll(bad);
+            if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
             if ((tid & 63) == 0) {
                 s_mx[tid >> 6] = mx;
-                s_my[tid >> 6] = my;
                 s_bad[tid >> 6] = bad;
             }
         }
         __syncthreads();   // LDS reuse by the next tile
-        if (mode == MODE_S3 && tid < 64) {
-            const double mx = tid < 4 ? s_mx[tid] : 0.0;
-            const double my = tid < 4 ? s_my[tid] : 0.0;
-            const long long bad = tid < 4 ? s_bad[tid] : LLONG_MAX;
-            publish_next_speeds(a.probs[tile.prob], mx, my, bad);
+        if (mode == MODE_S3 && tid == 0) {
+            double mx = s_mx[0];
+            long long bad = s_bad[0];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) {
+                mx = fmax(mx, s_mx[w]);
+                bad = s_bad[w] < bad ? s_bad[w] : bad;
+            }
+            publish_reduced(a.probs[tile.prob], mx, 0.0, bad);
         }
     }
 }

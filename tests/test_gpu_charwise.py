@@ -1,6 +1,7 @@
 """GPU parity of the reconstruction in local characteristic variables (1D
-Euler; remark closing Sec. 2.2) against the oracle, on the shock tubes of
-Sec. 3.2 and uneven batches.  Bars as for the component-wise path: FP64
+and 2D Euler; remark closing Sec. 2.2) against the oracle, on the shock
+tubes of Sec. 3.2, 2D Riemann/vortex data with every boundary type, and
+uneven batches.  Bars as for the component-wise path: FP64
 1e-12 per operator and step against natural scales, 1e-10 on whole runs;
 FP32 bulk 2e-5 in relative L1 of the averages."""
 import numpy as np
@@ -106,8 +107,130 @@ def test_charwise_batched_uneven_problems():
     assert steps == nmax
 
 
-def test_charwise_2d_is_rejected_for_now():
-    spec, st = W.quadrant_vortex_2d(16, seed=3)
+# ------------------------------------------------------------------ 2D --
+
+def _box(n, seed):
+    spec, st = W.quadrant_vortex_2d(n, seed=seed)
+    spec = W.Spec(dim=2, flux=W.EULER, nx=n, ny=n, xlo=spec.xlo, xhi=spec.xhi, ylo=spec.ylo,
+                  yhi=spec.yhi, bc_x=W.REFLECTIVE, bc_y=W.REFLECTIVE, t_end=0.05, name="box")
+    return spec, st
+
+
+def _nonsquare():
+    spec = W.Spec(dim=2, flux=W.EULER, nx=130, ny=70, xlo=0, xhi=1.3, ylo=0, yhi=0.7,
+                  bc_x=W.TRANSMISSIVE, bc_y=W.PERIODIC, t_end=0.1, name="nonsquare")
+    rng = np.random.default_rng(5)
+    J, I = np.meshgrid(np.arange(70), np.arange(130), indexing="ij")
+    rho = 0.5 + 0.3 * (I > 60) + 0.1 * np.sin(0.2 * I + 0.3 * J)
+    u = 0.3 * np.cos(0.1 * J)
+    v = -0.2 + 0.1 * (J > 40)
+    p = 0.7 + 0.2 * (I + J > 90)
+    st = np.zeros(spec.shape())
+    st[0] = W.conserved_2d(rho, u, v, p)
+    st[1] = 0.05 * rng.normal(size=st[1].shape)
+    st[2] = 0.05 * rng.normal(size=st[2].shape)
+    return spec, st
+
+
+CASES_2D = {
+    "quadrant-vortex-96": lambda: W.quadrant_vortex_2d(96, seed=7),
+    "nonsquare-130x70-transmissive": _nonsquare,
+    "walls-70": lambda: _box(70, seed=8),
+    "smooth-40": lambda: W.euler_2d_smooth(40),
+}
+
+
+@pytest.mark.parametrize("Q", [2, 3])
+@pytest.mark.parametrize("case", list(CASES_2D))
+def test_charwise_2d_rhs_and_step_f64(case, Q):
+    """2D Euler in characteristic variables (x and y eigenvectors of each
+    cell's average): operator, hats and one step against the oracle, plane
+    by plane at 1e-12 of the natural scales or 10x the oracle's own
+    sensitivity to 1e-15 input perturbations where that is larger."""
+    spec, st = CASES_2D[case]()
+    cfg = hw.default_config(2, precision=hw.F64, gauss_q=Q, characteristic=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        ax, ay = h.alpha(0)
+        L, Uh = h.rhs(0)
+        dt = h.step(want_dt=True)[0]
+        gpu, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    assert p.charwise == 1
+    S = natural_scales(spec, st)
+    SL = rhs_scales(spec, st, ax, ay)
+    Lr, Uhr = O.rhs(p, st, ax, ay)
+    ref = O.step(p, st, ax, ay, dt)
+    checks = [(Uh, Uhr, S, lambda s: O.rhs(p, s, ax, ay)[1]),
+              (L, Lr, SL, lambda s: O.rhs(p, s, ax, ay)[0]),
+              (gpu, ref, S, lambda s: O.step(p, s, ax, ay, dt))]
+    for got, want, sc, fn in checks:
+        ok, err, bar = within_conditioning(got, want, sc, oracle_sensitivity(fn, st, sc), 1e-12)
+        assert ok, (err, bar)
+    # the projection is not a no-op on these data
+    if case != "smooth-40":
+        p0 = oproblem(spec, hw.default_config(2, precision=hw.F64, gauss_q=Q))
+        assert scaled_err(O.rhs(p0, st, ax, ay)[0], Lr, SL) > 1e-6
+
+
+@pytest.mark.parametrize("prec", [hw.F32, hw.F32_ACC64, hw.F32_KAHAN])
+def test_charwise_2d_reduced_precision(prec):
+    spec, st = W.quadrant_vortex_2d(96, seed=7)
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, characteristic=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dts = [h.step(want_dt=True)[0] for _ in range(3)]
+        gpu, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    ref = st
+    for dt in dts:
+        ax, ay = O.alpha(p, ref)
+        ref = O.step(p, ref, ax, ay, dt)
+    assert l1_rel(gpu[0], ref[0]) < 2e-5, l1_rel(gpu[0], ref[0])
+
+
+@pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F32_KAHAN])
+def test_charwise_2d_conserves_cell_average_totals(prec):
+    spec, st = W.euler_2d_smooth(64)
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, characteristic=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        for _ in range(5):
+            h.step()
+        gpu, _ = h.get_state(0)
+    tot0 = st[0].sum(axis=(1, 2))
+    assert np.all(np.abs(gpu[0].sum(axis=(1, 2)) - tot0) <= 1e-12 * np.abs(tot0))
+
+
+def test_charwise_2d_independent_of_tiling_and_graphs():
+    spec, st = W.quadrant_vortex_2d(130, seed=2)
+    cfg = hw.default_config(2, precision=hw.F32_ACC64, gauss_q=2, characteristic=1)
+    outs = []
+    for rows, grid, graph in [(32, 0, 1), (8, 0, 0), (64, 37, 1)]:
+        with hw.Handle([spec], cfg) as h:
+            h.set_state(0, st)
+            h.set_tuning(tile_rows=rows, grid_blocks=grid, use_graph=graph)
+            for _ in range(3):
+                h.step()
+            outs.append(h.get_state(0)[0])
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
+def test_charwise_2d_batched_uneven_problems():
+    entries = W.batched_2d(seed=3, nprob=5, nmin=20, nmax=90)
+    specs = [e[0] for e in entries]
+    states = [W.batched_2d_state(e) for e in entries]
     cfg = hw.default_config(2, precision=hw.F64, gauss_q=2, characteristic=1)
-    with pytest.raises(hw.HwenoError):
-        hw.Handle([spec], cfg)
+    with hw.Handle(specs, cfg) as h:
+        for i, s in enumerate(states):
+            h.set_state(i, s)
+        dts = h.step(want_dt=True)
+        outs = [h.get_state(i)[0] for i in range(len(specs))]
+    for spec, s, dt, g in zip(specs, states, dts, outs):
+        p = oproblem(spec, cfg)
+        ax, ay = O.alpha(p, s)
+        S = natural_scales(spec, s)
+        fn = lambda x: O.step(p, x, ax, ay, dt)   # noqa: E731
+        ok, err, bar = within_conditioning(g, fn(s), S, oracle_sensitivity(fn, s, S), 1e-12)
+        assert ok, (spec.name, err, bar)
