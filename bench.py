@@ -32,12 +32,12 @@ VEC_TFLOPS = 78.6              # MI355X vector FP64, = non-packed FP32 (FMA coun
 # FP operations per cell-stage of the 2D Euler stage (Q = 2), from the FP
 # instruction counters of the stage kernel restricted to output-producing
 # lanes and rows (profiles/stage2d_euler2048.md)
-ALU_FLOP_PER_CELL_STAGE = 2750.0
+ALU_FLOP_PER_CELL_STAGE = 2764.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) for the kernel sources of this hash; any change of
 # the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "dfc83f45d7b9875d"
-PROFILED_TRAFFIC = {"f32acc64": 816.5e6, "f64": 1228.7e6}
+PROFILED_SOURCES = "ed9d4dc22742c82e"
+PROFILED_TRAFFIC = {"f32acc64": 832.1e6, "f64": 1246.2e6}
 
 
 def kernel_sources_hash() -> str:
@@ -175,11 +175,14 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    runs = [("f32acc64", hw.F32_ACC64, 8, 4), ("f64", hw.F64, 8, 8)]
+    runs = [("f32acc64", hw.F32_ACC64, 8, 4, 0), ("f64", hw.F64, 8, 8, 0)]
     if args.precision != "both":
         runs = [r for r in runs if r[0] == args.precision]
-    for name, prec, su, sd in runs:
-        cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
+    elif not args.profile_only:
+        # the same workload with the reconstruction in characteristic variables
+        runs.append(("f32acc64_characteristic", hw.F32_ACC64, 8, 4, 1))
+    for name, prec, su, sd, charwise in runs:
+        cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5, characteristic=charwise)
         ws = torch.empty(hw.Handle.workspace_bytes([spec], cfg), dtype=torch.uint8, device=dev)
         stream = torch.cuda.current_stream(dev)
         h = hw.Handle([spec], cfg, workspace=ws, stream=stream.cuda_stream)
@@ -272,6 +275,8 @@ def main():
         "fp64_path": {"value": f64_r["value"], "ms_per_step": f64_r["ms_per_step"],
                       "stage_kernel_ms": f64_r["stage_kernel_ms"],
                       "bytes_per_cell_stage": f64_r["bytes_per_cell_stage"]},
+        "characteristic_path": {k: results["f32acc64_characteristic"][k]
+                                for k in ("value", "ms_per_step", "stage_kernel_ms")},
         "l1_f32_vs_f64_after_timed_steps": l1_32_vs_64,
         "stage_kernel_ms": main_r["stage_kernel_ms"],
         "tuning": main_r.get("tuning"),
