@@ -265,38 +265,62 @@ __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, doubl
 // and m_t across it; columns of R (rows of L = R^-1) belong to the
 // eigenvalues v_n - c, v_n, [v_n (shear),] v_n + c.
 template <class T, int K> struct Eigen {
-    T R[K][K], L[K][K];
+    // the entries are closed forms in these scalars; no matrix is stored, so
+    // that rows picked by a run-time index stay in registers
+    T vn, vt, c, H, hq2, b1, b2, ec, hb1;
     __device__ __forceinline__ Eigen(const T* U, T gm1) {
         const T ir = rcp(U[0]);
-        const T vn = U[1] * ir;
-        const T vt = K == 4 ? U[2] * ir : (T)0;
-        const T hq2 = (T)0.5 * (vn * vn + vt * vt);
+        vn = U[1] * ir;
+        vt = K == 4 ? U[2] * ir : (T)0;
+        hq2 = (T)0.5 * (vn * vn + vt * vt);
         const T p = gm1 * (U[K - 1] - U[0] * hq2);
         const T c2 = (gm1 + (T)1) * p * ir;
-        const T c = sqrt(c2);
+        c = sqrt(c2);
         const T ic = rcp(c);
-        const T H = (U[K - 1] + p) * ir;
-        const T b1 = gm1 * ic * ic, b2 = b1 * hq2;
-        const T ec = (T)0.5 * ic;
-        const T hb1 = (T)0.5 * b1;
-        if constexpr (K == 3) {
-            R[0][0] = 1;          R[0][1] = 1;   R[0][2] = 1;
-            R[1][0] = vn - c;     R[1][1] = vn;  R[1][2] = vn + c;
-            R[2][0] = H - vn * c; R[2][1] = hq2; R[2][2] = H + vn * c;
-            L[0][0] = (T)0.5 * b2 + vn * ec; L[0][1] = -(hb1 * vn + ec); L[0][2] = hb1;
-            L[1][0] = (T)1 - b2;             L[1][1] = b1 * vn;          L[1][2] = -b1;
-            L[2][0] = (T)0.5 * b2 - vn * ec; L[2][1] = ec - hb1 * vn;    L[2][2] = hb1;
-        } else {
-            R[0][0] = 1;          R[0][1] = 1;   R[0][2] = 0;  R[0][3] = 1;
-            R[1][0] = vn - c;     R[1][1] = vn;  R[1][2] = 0;  R[1][3] = vn + c;
-            R[2][0] = vt;         R[2][1] = vt;  R[2][2] = 1;  R[2][3] = vt;
-            R[3][0] = H - vn * c; R[3][1] = hq2; R[3][2] = vt; R[3][3] = H + vn * c;
-            L[0][0] = (T)0.5 * b2 + vn * ec; L[0][1] = -(hb1 * vn + ec);
-            L[0][2] = -hb1 * vt;             L[0][3] = hb1;
-            L[1][0] = (T)1 - b2; L[1][1] = b1 * vn; L[1][2] = b1 * vt; L[1][3] = -b1;
-            L[2][0] = -vt;       L[2][1] = 0;       L[2][2] = 1;       L[2][3] = 0;
-            L[3][0] = (T)0.5 * b2 - vn * ec; L[3][1] = ec - hb1 * vn;
-            L[3][2] = -hb1 * vt;             L[3][3] = hb1;
+        H = (U[K - 1] + p) * ir;
+        b1 = gm1 * ic * ic;
+        b2 = b1 * hq2;
+        ec = (T)0.5 * ic;
+        hb1 = (T)0.5 * b1;
+    }
+    // L[i][k] (row i: field, column k: component), constant indices
+    __device__ __forceinline__ T L(int i, int k) const {
+        if (K == 3) {
+            if (i == 1) return k == 0 ? (T)1 - b2 : (k == 1 ? b1 * vn : -b1);
+            const T s = i == 0 ? (T)1 : (T)-1;   // fields v-c (0) and v+c (2)
+            return k == 0 ? (T)0.5 * b2 + s * vn * ec : (k == 1 ? -(hb1 * vn) - s * ec : hb1);
+        }
+        if (i == 1) return k == 0 ? (T)1 - b2 : (k == 1 ? b1 * vn : (k == 2 ? b1 * vt : -b1));
+        if (i == 2) return k == 0 ? -vt : (k == 2 ? (T)1 : (T)0);
+        const T s = i == 0 ? (T)1 : (T)-1;       // fields v-c (0) and v+c (3)
+        return k == 0 ? (T)0.5 * b2 + s * vn * ec
+                      : (k == 1 ? -(hb1 * vn) - s * ec : (k == 2 ? -hb1 * vt : hb1));
+    }
+    // R[i][k] (row i: component, column k: field), constant indices
+    __device__ __forceinline__ T R(int i, int k) const {
+        const int kc = K == 3 ? (k == 2 ? 3 : k) : k;   // 1D has no shear field
+        if (i == 0) return kc == 2 ? (T)0 : (T)1;
+        if (i == 1) return kc == 0 ? vn - c : (kc == 3 ? vn + c : (kc == 1 ? vn : (T)0));
+        if (K == 4 && i == 2) return kc == 2 ? (T)1 : vt;
+        return kc == 0 ? H - vn * c : (kc == 3 ? H + vn * c : (kc == 1 ? hq2 : vt));
+    }
+    // row i of L or of R for a run-time (wave-uniform) i
+    __device__ __forceinline__ void lrow(int i, T* out) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            T v = L(K - 1, k);
+#pragma unroll
+            for (int j = K - 2; j >= 0; --j) v = i == j ? L(j, k) : v;
+            out[k] = v;
+        }
+    }
+    __device__ __forceinline__ void rrow(int i, T* out) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            T v = R(K - 1, k);
+#pragma unroll
+            for (int j = K - 2; j >= 0; --j) v = i == j ? R(j, k) : v;
+            out[k] = v;
         }
     }
     // w = L x and x = R w (vectors in the (rho, m_n, [m_t,] E) order)
@@ -305,17 +329,17 @@ template <class T, int K> struct Eigen {
         for (int k = 0; k < K; ++k) {
             T a = 0;
 #pragma unroll
-            for (int c = 0; c < K; ++c) a += L[k][c] * x[c];
+            for (int j = 0; j < K; ++j) a += L(k, j) * x[j];
             w[k] = a;
         }
     }
     __device__ __forceinline__ void right(const T* w, T* x) const {
 #pragma unroll
-        for (int c = 0; c < K; ++c) {
+        for (int i = 0; i < K; ++i) {
             T a = 0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) a += R[c][k] * w[k];
-            x[c] = a;
+            for (int k = 0; k < K; ++k) a += R(i, k) * w[k];
+            x[i] = a;
         }
     }
 };

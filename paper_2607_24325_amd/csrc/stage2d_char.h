@@ -179,11 +179,14 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
                 for (int k = 0; k < K; ++k) Uy[k] = Uc[PY[k]];
                 const Eigen<T, K> ex(Uc, gm1);
                 const Eigen<T, K> ey(Uy, gm1);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    Rx[k] = ex.R[c][k];
-                    Ry[k] = ey.R[PY[c]][k];
-                }
+                // row c of R_x; row PY[c] of R_y (component c in y order); row
+                // c of L_x and of L_y (field c)
+                const int cy = c == 1 ? 2 : (c == 2 ? 1 : c);
+                T Lx[K], Ly[K];
+                ex.rrow(c, Rx);
+                ey.rrow(cy, Ry);
+                ex.lrow(c, Lx);
+                ey.lrow(c, Ly);
 #pragma unroll
                 for (int e = 0; e < 17; ++e) {
                     wx[e] = 0;
@@ -212,7 +215,7 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
                     q[16] = (T)rW[sp][k][lane];
                     // storage component k is position k of the x order and
                     // position PY[k] of the y order
-                    const T lx = ex.L[c][k], ly = ey.L[c][PY[k]];
+                    const T lx = Lx[k], ly = Ly[PY[k]];
 #pragma unroll
                     for (int e = 0; e < 17; ++e) {
                         wx[e] += lx * q[e];
