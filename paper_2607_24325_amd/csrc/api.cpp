@@ -706,7 +706,7 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     if (h->dim == 1) {
         for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cands.push_back({64, g, 1, 0});
     } else {
-        for (int rows : {16, 32, 64, 128, 256})
+        for (int rows : {16, 24, 32, 48, 64, 128})
             for (int g : {0, 2 * ncu}) cands.push_back({rows, g, 1, 0});
     }
     hweno_tuning keep = h->tun, win = h->tun;

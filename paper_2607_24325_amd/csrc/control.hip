@@ -39,22 +39,34 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
         const TU* base = U + P_.off_u;
         double mx = 0.0, my = 0.0;
         long long bad = LLONG_MAX;
-        for (int k = threadIdx.x; k < chunk.count; k += 256) {
-            const int64_t idx = chunk.start + k;
-            double u[K];
+        // every load of the thread's cells first (lanes past the chunk read
+        // its first cell), then the speeds
+        constexpr int PER = CHUNK_CELLS / 256;
+        double u[PER][K];
 #pragma unroll
-            for (int c = 0; c < K; ++c) u[c] = (double)base[c * plane + idx];
-            double sx, sy;
-            if (wave_speed<FLUX, DIM, K>(u, sch, sx, sy)) {
-                mx = fmax(mx, sx);
-                my = fmax(my, sy);
-            } else if (idx < bad) {
-                bad = idx;
+        for (int j = 0; j < PER; ++j) {
+            const int k = threadIdx.x + 256 * j;
+            const int64_t idx = chunk.start + (k < chunk.count ? k : 0);
+#pragma unroll
+            for (int c = 0; c < K; ++c) u[j][c] = (double)base[c * plane + idx];
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = threadIdx.x + 256 * j;
+            if (k < chunk.count) {
+                double sx, sy;
+                if (wave_speed<FLUX, DIM, K>(u[j], sch, sx, sy)) {
+                    mx = fmax(mx, sx);
+                    my = fmax(my, sy);
+                } else {
+                    const int64_t idx = chunk.start + k;
+                    if (idx < bad) bad = idx;
+                }
             }
         }
         mx = wave_max_d(mx);
         my = wave_max_d(my);
-        bad = wave_min_ll(bad);
+        if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
         const int wv = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             smx[wv] = mx;

@@ -192,6 +192,26 @@ def test_results_independent_of_tiling_and_graphs():
         np.testing.assert_array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F64, hw.F32_KAHAN])
+def test_fused_wave_speeds_equal_a_fresh_reduction(prec):
+    """Stage 3 gathers the wave speeds of the state it writes (in groups of
+    rows, one wave per row of a group); the next step's time step must be
+    exactly the one that the speeds of that state give.  Segment heights
+    that leave partial groups and a last short segment are included."""
+    spec, st = _nonsquare()
+    cfg = hw.default_config(2, precision=prec, gauss_q=2)
+    p = oproblem(spec, cfg)
+    for rows in (8, 13, 32, 64):
+        with _one(spec, st, cfg) as h:
+            h.set_tuning(tile_rows=rows)
+            h.step()
+            for _ in range(3):
+                cur, _ = h.get_state(0)
+                ax, ay = O.alpha(p, cur)
+                dt = h.step(want_dt=True)[0]
+                assert dt == O.dt(p, ax, ay, cfg.cfl), (rows, dt, O.dt(p, ax, ay, cfg.cfl))
+
+
 # -------------------------------------------------------------- batching --
 
 def test_batched_2d_uneven_problems():
