@@ -104,12 +104,20 @@ typedef struct {
                              variables of each cell's own average (remark
                              closing Sec. 2.2), 0 = per conserved
                              component; scalar laws ignore it             */
-    int32_t reserved_;    /* zero                                           */
+    int32_t smoothness;   /* indicator beta_0 of p0: HWENO_BETA_MOMENT (the
+                             paper's, eq. smoothness-indicator: squared
+                             scaled derivatives at the cell centre) or
+                             HWENO_BETA_CLASSICAL (the integral form it is
+                             compared with, eq. smoothness-indicator-
+                             typical and its 2D form)                     */
 } hweno_config;
+
+enum { HWENO_BETA_MOMENT = 0, HWENO_BETA_CLASSICAL = 1 };
 
 /* Fills cfg with the paper's settings for dimension dim: gamma = 1/400 per
  * linear polynomial and the rest on p0 (Sec. 3), eps = 1e-8, CFL 0.6, Q = 3,
- * W_BETA, F64, dt_exponent 1, component-wise reconstruction. */
+ * W_BETA, F64, dt_exponent 1, component-wise reconstruction, the moment
+ * smoothness indicator. */
 void hweno_default_config(int32_t dim, hweno_config* cfg);
 
 /* Bytes of device memory hweno_create needs for these problems, so that a

@@ -25,6 +25,7 @@ SRC_PATH = os.path.join(HERE, "hweno_oracle.c")
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 W_PAPER, W_BETA, W_BETA2, W_LINEAR = 0, 1, 2, 3
+BETA_MOMENT, BETA_CLASSICAL = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -44,7 +45,8 @@ class _Problem(C.Structure):
                 ("yhi", C.c_double), ("bc_x", C.c_int), ("bc_y", C.c_int),
                 ("gas_gamma", C.c_double), ("adv", C.c_double * 2),
                 ("gauss_q", C.c_int), ("weights", C.c_int),
-                ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("charwise", C.c_int)]
+                ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("charwise", C.c_int),
+                ("smoothness", C.c_int)]
 
 
 @dataclass
@@ -66,6 +68,7 @@ class Problem:
     gamma_lin: tuple = field(default=None)
     eps: float = 1e-8
     charwise: int = 0
+    smoothness: int = BETA_MOMENT
 
     def __post_init__(self):
         if self.gamma_lin is None:
@@ -99,7 +102,8 @@ class Problem:
         return _Problem(self.dim, self.flux, self.nx, self.ny, self.xlo, self.xhi,
                         self.ylo, self.yhi, self.bc_x, self.bc_y, self.gas_gamma,
                         (C.c_double * 2)(*self.adv), self.gauss_q, self.weights,
-                        (C.c_double * 5)(*g), self.eps, int(self.charwise))
+                        (C.c_double * 5)(*g), self.eps, int(self.charwise),
+                        int(self.smoothness))
 
 
 _lib = None
@@ -118,6 +122,10 @@ def lib():
         L.orc_euler_eigen.argtypes = [P, C.c_int, _D, _D, _D, _D]
         L.orc_recon_char_1d.argtypes = [P, _D, _D, C.c_double, _D]
         L.orc_recon_char_2d.argtypes = [P, _D, C.c_int, _D]
+        L.orc_smoothness_classical_1d.argtypes = [_D]
+        L.orc_smoothness_classical_1d.restype = C.c_double
+        L.orc_smoothness_classical_2d.argtypes = [_D]
+        L.orc_smoothness_classical_2d.restype = C.c_double
         L.orc_poly2d_eval.argtypes = [_D, C.c_double, C.c_double, _D]
         L.orc_poly2d_eval.restype = None
         L.orc_flux.argtypes = [P, C.c_int, _D, _D, _D, _D]
@@ -217,6 +225,15 @@ def recon_char_2d(p: Problem, q, direction: int) -> dict:
            "recon_char_2d")
     K = p.K
     return {"C": out[:15 * K].reshape(K, 15), "vhat": out[15 * K:16 * K], "what": out[16 * K:]}
+
+
+def smoothness_classical(c) -> float:
+    """classical indicator of a polynomial: 5 (1D) or 15 (2D) coefficients"""
+    c = _f64(c)
+    if c.size == 5:
+        return float(lib().orc_smoothness_classical_1d(_ptr(c)))
+    assert c.size == 15
+    return float(lib().orc_smoothness_classical_2d(_ptr(c)))
 
 
 def poly2d_eval(Cc, xi: float, eta: float) -> np.ndarray:

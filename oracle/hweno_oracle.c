@@ -195,6 +195,35 @@ static void nonlinear_weights(const orc_problem* p, int M, const double* beta,
     for (int m = 0; m <= M; ++m) omega[m] = wt[m] / sum;
 }
 
+/* Classical smoothness indicator (eq. smoothness-indicator-typical and its 2D
+ * form eq. smoothness-indicator-typical-2D), in cell units xi = (x - x_i)/dx:
+ * the powers of dx cancel, leaving the sum over derivative orders of the
+ * integrals of the squared derivatives over [-1/2, 1/2] (per variable).  The
+ * integrals use the 4-point Gauss-Legendre rule per variable, exact for the
+ * squared derivatives of a quartic (degree <= 6). */
+static const double GL4_X[4] = {-0.43056815579702629, -0.16999052179242813,
+                                0.16999052179242813, 0.43056815579702629};
+static const double GL4_W[4] = {0.17392742256872693, 0.32607257743127307,
+                                0.32607257743127307, 0.17392742256872693};
+
+/* k (k-1) ... (k-m+1): the factor that the m-th derivative puts on xi^k */
+static double falling(int k, int m) {
+    double r = 1.0;
+    for (int i = 0; i < m; ++i) r *= (double)(k - i);
+    return r;
+}
+
+double orc_smoothness_classical_1d(const double c[5]) {
+    double b = 0.0;
+    for (int l = 1; l <= 4; ++l)
+        for (int q = 0; q < 4; ++q) {
+            double d = 0.0;
+            for (int k = l; k <= 4; ++k) d += c[k] * falling(k, l) * pow(GL4_X[q], k - l);
+            b += GL4_W[q] * d * d;
+        }
+    return b;
+}
+
 static void recon_1d(const orc_problem* p, const double ub[3], double vm, double vp,
                      double dx, recon1d_t* r) {
     /* Appendix A: p0 matches the three cell averages and the derivative means
@@ -218,7 +247,7 @@ static void recon_1d(const orc_problem* p, const double ub[3], double vm, double
     static const double fact[5] = {1.0, 1.0, 2.0, 6.0, 24.0};
     double b0 = 0.0;
     for (int l = 1; l <= 4; ++l) b0 += (fact[l] * r->c0[l]) * (fact[l] * r->c0[l]);
-    r->beta[0] = b0;
+    r->beta[0] = p->smoothness == ORC_BETA_CLASSICAL ? orc_smoothness_classical_1d(r->c0) : b0;
     r->beta[1] = r->c1[1] * r->c1[1];
     r->beta[2] = r->c2[1] * r->c2[1];
 
@@ -283,6 +312,25 @@ int orc_recon_1d(const orc_problem* p, const double ub[3], const double vb[2], d
 static const int MEXP[15] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
 static const int NEXP[15] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
 
+double orc_smoothness_classical_2d(const double c[15]) {
+    double b = 0.0;
+    for (int m = 0; m <= 4; ++m)
+        for (int n = 0; m + n <= 4; ++n) {
+            if (m + n == 0) continue;
+            for (int q = 0; q < 4; ++q)
+                for (int s = 0; s < 4; ++s) {
+                    double d = 0.0;
+                    for (int k = 0; k < 15; ++k) {
+                        if (MEXP[k] < m || NEXP[k] < n) continue;
+                        d += c[k] * falling(MEXP[k], m) * falling(NEXP[k], n) *
+                             pow(GL4_X[q], MEXP[k] - m) * pow(GL4_X[s], NEXP[k] - n);
+                    }
+                    b += GL4_W[q] * GL4_W[s] * d * d;
+                }
+        }
+    return b;
+}
+
 typedef struct {
     double c0[15];
     double lin[4][3]; /* p_1..p_4: constant, xi, eta coefficients */
@@ -344,7 +392,7 @@ static void recon_2d(const orc_problem* p, const double* q, recon2d_t* r) {
         double s = fact[MEXP[l]] * fact[NEXP[l]] * r->c0[l];
         b0 += s * s;
     }
-    r->beta[0] = b0;
+    r->beta[0] = p->smoothness == ORC_BETA_CLASSICAL ? orc_smoothness_classical_2d(r->c0) : b0;
     for (int m = 0; m < 4; ++m)
         r->beta[m + 1] = r->lin[m][1] * r->lin[m][1] + r->lin[m][2] * r->lin[m][2];
 
@@ -1022,6 +1070,7 @@ static int check_problem(const orc_problem* p) {
     if (p->dim == 1 && p->ny != 1) return -1;
     if (p->nx < 4 || (p->dim == 2 && p->ny < 4)) return -1;
     if (p->dim == 2 && gauss_rule(p->gauss_q, (double[3]){0}, (double[3]){0})) return -1;
+    if (p->smoothness != ORC_BETA_MOMENT && p->smoothness != ORC_BETA_CLASSICAL) return -1;
     if (p->bc_x < ORC_PERIODIC || p->bc_x > ORC_REFLECTIVE) return -1;
     if (p->dim == 2 && (p->bc_y < ORC_PERIODIC || p->bc_y > ORC_REFLECTIVE)) return -1;
     if (p->flux != ORC_EULER && (p->bc_x == ORC_REFLECTIVE ||

@@ -27,6 +27,7 @@ extern "C" {
 enum { ORC_ADVECTION = 0, ORC_BURGERS = 1, ORC_EULER = 2 };
 enum { ORC_PERIODIC = 0, ORC_TRANSMISSIVE = 1, ORC_REFLECTIVE = 2 };
 enum { ORC_W_PAPER = 0, ORC_W_BETA = 1, ORC_W_BETA2 = 2, ORC_W_LINEAR = 3 };
+enum { ORC_BETA_MOMENT = 0, ORC_BETA_CLASSICAL = 1 };
 
 typedef struct {
     int dim;               /* 1 or 2 */
@@ -45,6 +46,9 @@ typedef struct {
     double eps;            /* epsilon of the nonlinear weights */
     int charwise;          /* Euler: 1 = reconstruct and modify in local
                               characteristic variables, 0 = per component */
+    int smoothness;        /* indicator of p0: ORC_BETA_MOMENT (the paper's,
+                              eq. smoothness-indicator) or ORC_BETA_CLASSICAL
+                              (eq. smoothness-indicator-typical, -2D) */
 } orc_problem;
 
 /* Number of conserved components K of the problem. */
@@ -64,6 +68,13 @@ int orc_recon_1d(const orc_problem* p, const double ub[3], const double vb[2],
  *   vhat what.  Basis order 1, xi, eta, xi^2, xi*eta, eta^2, xi^3, xi^2 eta,
  * xi eta^2, eta^3, xi^4, xi^3 eta, xi^2 eta^2, xi eta^3, eta^4. */
 int orc_recon_2d(const orc_problem* p, const double q[17], double* out);
+
+/* Classical smoothness indicator of a polynomial given by its monomial
+ * coefficients in cell units (1D: c[5] of 1, xi, .., xi^4; 2D: c[15] in the
+ * basis order above): the sum over all derivative orders >= 1 of the
+ * integral over the cell of the squared derivative. */
+double orc_smoothness_classical_1d(const double c[5]);
+double orc_smoothness_classical_2d(const double c[15]);
 
 /* Evaluate a 2D combined polynomial C[15] at local (xi, eta):
  * out = (U, dU/dxi, dU/deta). */

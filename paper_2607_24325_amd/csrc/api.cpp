@@ -143,6 +143,8 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
     if (!(cfg->dt_exponent > 0.0)) return fail(h, HWENO_ERR_ARG, "dt_exponent must be positive");
     if (cfg->characteristic != 0 && cfg->characteristic != 1)
         return fail(h, HWENO_ERR_ARG, "characteristic must be 0 or 1");
+    if (cfg->smoothness != HWENO_BETA_MOMENT && cfg->smoothness != HWENO_BETA_CLASSICAL)
+        return fail(h, HWENO_ERR_ARG, "unknown smoothness indicator %d", cfg->smoothness);
     return HWENO_OK;
 }
 
@@ -320,6 +322,7 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     h->sch.weights = cfg->weights;
     h->sch.Q = cfg->gauss_q;
     h->sch.charwise = cfg->characteristic && h->flux == F_EULER;
+    h->sch.smoothness = cfg->smoothness;
 
     // problem table
     h->h_probs.resize(nprob);

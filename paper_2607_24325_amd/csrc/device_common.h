@@ -257,6 +257,84 @@ __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, doubl
     if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad);
 }
 
+// --------------------------------------- classical smoothness indicator ---
+//
+// The indicator the paper prints for comparison with its own (eq.
+// smoothness-indicator-typical and its 2D form): in cell units, the sum over
+// derivative orders >= 1 of the integrals over the cell of the squared
+// derivatives.  For p = sum_i c_i xi^a_i eta^b_i it is the quadratic form
+// sum_ij c_i c_j M_ij, M_ij = sum_(m,n) (a_i)_m (a_j)_m (b_i)_n (b_j)_n
+// mu(a_i + a_j - 2m) mu(b_i + b_j - 2n), with (a)_m the falling factorial
+// and mu(k) the k-th moment of [-1/2, 1/2].  The entries are evaluated at
+// compile time.
+namespace classical {
+constexpr double moment(int k) {
+    if (k % 2) return 0.0;
+    double p = 1.0;
+    for (int i = 0; i < k; ++i) p *= 0.5;
+    return p / (k + 1);
+}
+constexpr double falling(int a, int m) {
+    double r = 1.0;
+    for (int i = 0; i < m; ++i) r *= (double)(a - i);
+    return r;
+}
+constexpr double entry(int ai, int bi, int aj, int bj) {
+    double s = 0.0;
+    for (int m = 0; m <= 4; ++m)
+        for (int n = 0; m + n <= 4; ++n) {
+            if (m + n == 0 || m > ai || m > aj || n > bi || n > bj) continue;
+            s += falling(ai, m) * falling(aj, m) * falling(bi, n) * falling(bj, n) *
+                 moment(ai + aj - 2 * m) * moment(bi + bj - 2 * n);
+        }
+    return s;
+}
+// exponents of the 2D basis 1, xi, eta, xi^2, xi eta, eta^2, ... eta^4
+constexpr int EX[15] = {0, 1, 0, 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0};
+constexpr int EY[15] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4};
+template <int I, int J> struct E1 { static constexpr double v = entry(I, 0, J, 0); };
+template <int I, int J> struct E2 {
+    static constexpr double v = entry(EX[I], EY[I], EX[J], EY[J]);
+};
+
+template <class T, int I, int J>
+__device__ __forceinline__ void acc1(const T* c, T& b) {
+    if constexpr (I <= 4) {
+        if constexpr (J <= 4) {
+            constexpr double m = (I == J ? 1.0 : 2.0) * E1<I, J>::v;
+            if constexpr (m != 0.0) b += (T)m * c[I] * c[J];
+            acc1<T, I, J + 1>(c, b);
+        } else {
+            acc1<T, I + 1, I + 1>(c, b);
+        }
+    }
+}
+template <class T, int I, int J>
+__device__ __forceinline__ void acc2(const T* c, T& b) {
+    if constexpr (I <= 14) {
+        if constexpr (J <= 14) {
+            constexpr double m = (I == J ? 1.0 : 2.0) * E2<I, J>::v;
+            if constexpr (m != 0.0) b += (T)m * c[I] * c[J];
+            acc2<T, I, J + 1>(c, b);
+        } else {
+            acc2<T, I + 1, I + 1>(c, b);
+        }
+    }
+}
+}  // namespace classical
+
+// indicator of a 1D quartic c[0..4] / 2D quartic c[0..14] (constant ignored)
+template <class T> __device__ __forceinline__ T beta_classical_1d(const T* c) {
+    T b = 0;
+    classical::acc1<T, 1, 1>(c, b);
+    return b;
+}
+template <class T> __device__ __forceinline__ T beta_classical_2d(const T* c) {
+    T b = 0;
+    classical::acc2<T, 1, 1>(c, b);
+    return b;
+}
+
 // ------------------------------------------- characteristic variables ---
 //
 // Eigenvectors of the Euler flux Jacobian at a cell's own average, for the

@@ -10,6 +10,7 @@ namespace hweno {
 // Arithmetic modes (values match HWENO_F64 ... HWENO_F32_KAHAN).
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_ACC64 = 2, P_KAHAN = 3 };
 enum FluxKind : int { F_ADV = 0, F_BURGERS = 1, F_EULER = 2 };
+enum SmoothnessKind : int { BETA_MOMENT = 0, BETA_CLASSICAL = 1 };
 enum BC : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 enum WeightMode : int { W_PAPER = 0, W_BETA = 1, W_BETA2 = 2, W_LINEAR = 3 };
 
@@ -82,7 +83,7 @@ struct Scheme {
     int32_t weights;   // WeightMode
     int32_t Q;         // Gauss points per edge (2D)
     int32_t charwise;  // Euler: reconstruct in local characteristic variables
-    int32_t pad_;
+    int32_t smoothness;   // SmoothnessKind of p0's indicator
 };
 
 // Buffers of one state set in the internal layout.

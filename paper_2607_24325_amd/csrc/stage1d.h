@@ -93,8 +93,10 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
             c0v[3] = (T)0.25 * (dm - dp) + (T)0.25 * (dvm + dvp);
             c0v[4] = (T)-0.5 * (dm + dp) + (T)0.25 * (dvp - dvm);
             T beta[3];
-            beta[0] = c0v[1] * c0v[1] + (T)4 * c0v[2] * c0v[2] + (T)36 * c0v[3] * c0v[3] +
-                      (T)576 * c0v[4] * c0v[4];
+            beta[0] = sch.smoothness == BETA_CLASSICAL
+                          ? beta_classical_1d(c0v)
+                          : c0v[1] * c0v[1] + (T)4 * c0v[2] * c0v[2] + (T)36 * c0v[3] * c0v[3] +
+                                (T)576 * c0v[4] * c0v[4];
             beta[1] = dm * dm;
             beta[2] = dp * dp;
             T w[3];

@@ -89,7 +89,7 @@ __device__ __forceinline__ void reconstruct2d(const T* q, const Scheme& s, int s
     b0 += (T)36 * (c0[6] * c0[6] + c0[9] * c0[9] + c0[11] * c0[11] + c0[13] * c0[13]);
     b0 += (T)576 * (c0[10] * c0[10] + c0[14] * c0[14]);
     T beta[5];
-    beta[0] = b0;
+    beta[0] = s.smoothness == BETA_CLASSICAL ? beta_classical_2d(c0) : b0;
     const T sW2 = sW * sW, sE2 = sE * sE, sS2 = sS * sS, sN2 = sN * sN;
     beta[1] = sW2 + sS2;
     beta[2] = sE2 + sS2;

@@ -21,6 +21,7 @@ OK, ERR_ARG, ERR_NONFINITE, ERR_HIP, ERR_STATE, ERR_OOM = 0, -1, -2, -3, -4, -5
 ADVECTION, BURGERS, EULER = 0, 1, 2
 PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
 F64, F32, F32_ACC64, F32_KAHAN = 0, 1, 2, 3
+BETA_MOMENT, BETA_CLASSICAL = 0, 1
 W_PAPER, W_BETA, W_BETA2, W_LINEAR = 0, 1, 2, 3
 
 
@@ -35,7 +36,7 @@ class hweno_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gauss_q", C.c_int32), ("weights", C.c_int32),
                 ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("cfl", C.c_double),
                 ("dt_exponent", C.c_double), ("characteristic", C.c_int32),
-                ("reserved_", C.c_int32)]
+                ("smoothness", C.c_int32)]
 
 
 class hweno_tuning(C.Structure):

@@ -11,7 +11,8 @@ def oproblem(spec, cfg):
                      xhi=spec.xhi, ylo=spec.ylo, yhi=spec.yhi, bc_x=spec.bc_x, bc_y=spec.bc_y,
                      gas_gamma=spec.gas_gamma, adv=tuple(spec.adv), gauss_q=cfg.gauss_q,
                      weights=cfg.weights, gamma_lin=tuple(cfg.gamma_lin)[:3 if spec.dim == 1 else 5],
-                     eps=cfg.eps, charwise=int(cfg.characteristic))
+                     eps=cfg.eps, charwise=int(cfg.characteristic),
+                     smoothness=int(cfg.smoothness))
 
 
 def plane_rel(gpu, ref):

@@ -1,0 +1,122 @@
+"""GPU parity of the option variants against the oracle: the classical
+smoothness indicator of p0 (the integral form the paper prints for
+comparison, eq. smoothness-indicator-typical and its 2D form) in 1D and 2D,
+component-wise and in characteristic variables, and Q = 3 Gauss points on
+uneven batches.  Bars as elsewhere: 1e-12 of the natural scales per
+evaluation and step (or 10x the oracle's own sensitivity to 1e-15 input
+perturbations where larger), 2e-5 relative L1 for FP32 bulk."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import (oproblem, l1_rel, natural_scales, rhs_scales, oracle_sensitivity,
+                      within_conditioning, scaled_err)
+from paper_2607_24325_amd import hweno as hw
+from paper_2607_24325_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_rhs_and_step(spec, st, cfg):
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        ax, ay = h.alpha(0)
+        L, Uh = h.rhs(0)
+        dt = h.step(want_dt=True)[0]
+        gpu, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    ay = ay if spec.dim == 2 else 0.0
+    S = natural_scales(spec, st)
+    SL = rhs_scales(spec, st, ax, ay)
+    Lr, Uhr = O.rhs(p, st, ax, ay)
+    ref = O.step(p, st, ax, ay, dt)
+    for got, want, sc, fn in [(Uh, Uhr, S, lambda s: O.rhs(p, s, ax, ay)[1]),
+                              (L, Lr, SL, lambda s: O.rhs(p, s, ax, ay)[0]),
+                              (gpu, ref, S, lambda s: O.step(p, s, ax, ay, dt))]:
+        ok, err, bar = within_conditioning(got, want, sc, oracle_sensitivity(fn, st, sc), 1e-12)
+        assert ok, (err, bar)
+    return p, Lr
+
+
+CASES_1D = {
+    "riemann-600": lambda: W.riemann_1d(3, nx=600),
+    "lax-400": lambda: W.lax_1d(400),
+    "burgers-100": lambda: W.burgers_1d(100),
+}
+
+
+@pytest.mark.parametrize("charwise", [0, 1])
+@pytest.mark.parametrize("case", list(CASES_1D))
+def test_classical_indicator_1d(case, charwise):
+    spec, st = CASES_1D[case]()
+    cfg = hw.default_config(1, precision=hw.F64, characteristic=charwise,
+                            smoothness=hw.BETA_CLASSICAL)
+    p, Lr = _check_rhs_and_step(spec, st, cfg)
+    assert p.smoothness == O.BETA_CLASSICAL
+    # the option changes the operator on these data
+    p0 = oproblem(spec, hw.default_config(1, precision=hw.F64, characteristic=charwise))
+    ax, _ = O.alpha(p, st)
+    assert scaled_err(O.rhs(p0, st, ax, 0.0)[0], Lr, rhs_scales(spec, st, ax, 0.0)) > 1e-8
+
+
+@pytest.mark.parametrize("Q", [2, 3])
+@pytest.mark.parametrize("charwise", [0, 1])
+def test_classical_indicator_2d(Q, charwise):
+    spec, st = W.quadrant_vortex_2d(96, seed=7)
+    cfg = hw.default_config(2, precision=hw.F64, gauss_q=Q, characteristic=charwise,
+                            smoothness=hw.BETA_CLASSICAL)
+    _check_rhs_and_step(spec, st, cfg)
+
+
+@pytest.mark.parametrize("prec", [hw.F32, hw.F32_ACC64, hw.F32_KAHAN])
+def test_classical_indicator_reduced_precision(prec):
+    spec, st = W.quadrant_vortex_2d(96, seed=7)
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, smoothness=hw.BETA_CLASSICAL)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dts = [h.step(want_dt=True)[0] for _ in range(3)]
+        gpu, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    ref = st
+    for dt in dts:
+        ax, ay = O.alpha(p, ref)
+        ref = O.step(p, ref, ax, ay, dt)
+    assert l1_rel(gpu[0], ref[0]) < 2e-5, l1_rel(gpu[0], ref[0])
+
+
+def test_classical_indicator_smooth_advection_run():
+    """u_t + u_x = 0 to t = 2 with the classical indicator: same step count
+    and final state within 1e-10 of the oracle"""
+    spec, st = W.advection_1d(200)
+    cfg = hw.default_config(1, precision=hw.F64, smoothness=hw.BETA_CLASSICAL)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        steps = h.run_to_time()
+        gpu, t = h.get_state(0)
+    ref, n = O.run(oproblem(spec, cfg), st, 0.0, 2.0, cfg.cfl)
+    assert steps == n and t == 2.0
+    assert scaled_err(gpu, ref, natural_scales(spec, st)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [hw.F64, hw.F32_ACC64])
+def test_q3_batched_uneven_problems(prec):
+    entries = W.batched_2d(seed=5, nprob=6, nmin=20, nmax=110)
+    specs = [e[0] for e in entries]
+    states = [W.batched_2d_state(e) for e in entries]
+    cfg = hw.default_config(2, precision=prec, gauss_q=3, cfl=0.5)
+    with hw.Handle(specs, cfg) as h:
+        for i, s in enumerate(states):
+            h.set_state(i, s)
+        dts = h.step(want_dt=True)
+        outs = [h.get_state(i)[0] for i in range(len(specs))]
+    for spec, s, dt, g in zip(specs, states, dts, outs):
+        p = oproblem(spec, cfg)
+        ax, ay = O.alpha(p, s)
+        ref = O.step(p, s, ax, ay, dt)
+        if prec == hw.F64:
+            S = natural_scales(spec, s)
+            fn = lambda x: O.step(p, x, ax, ay, dt)   # noqa: E731
+            ok, err, bar = within_conditioning(g, ref, S, oracle_sensitivity(fn, s, S), 1e-12)
+            assert ok, (spec.name, err, bar)
+        else:
+            assert l1_rel(g[0], ref[0]) < 2e-5, (spec.name, l1_rel(g[0], ref[0]))
