@@ -89,7 +89,7 @@ def test_1d_quadratic_worked_example():
         expect = w[0] / g[0] * 0.25 + const
         assert abs(r["u_right"] - expect) < 1e-14 and abs(r["u_left"] - expect) < 1e-14
         assert abs(r["vhat"]) < 1e-14
-    # the survey's worked value for the beta + eps form
+    # the closed form above for the beta + eps form, as a fixed number
     r = O.recon_1d(p1d(O.W_BETA), ub, vb, 1.0)
     assert abs(r["u_right"] - 0.248287019432038) < 1e-12
 
@@ -203,7 +203,8 @@ def test_2d_quadratic_worked_example():
         np.testing.assert_allclose(r["omega"], wt / wt.sum(), rtol=1e-13)
         assert abs(r["vhat"]) < 1e-14 and abs(r["what"]) < 1e-14
     r = O.recon_2d(p2d(O.W_BETA2), q)
-    # the survey's worked values for the beta^2 + eps form
+    # the closed form for the beta^2 + eps form as fixed numbers: omega_0, and
+    # u, u_xi at the Gauss point (1/2, 1/(2 sqrt 3)) of the right face
     assert abs(r["omega"][0] - 0.939278937882) < 1e-11
     val = O.poly2d_eval(r["C"], 0.5, 0.5 / np.sqrt(3.0))
     assert abs(val[0] - 0.241461100654) < 1e-11
