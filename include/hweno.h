@@ -110,6 +110,11 @@ typedef struct {
                              HWENO_BETA_CLASSICAL (the integral form it is
                              compared with, eq. smoothness-indicator-
                              typical and its 2D form)                     */
+    int32_t alpha_stage;  /* 1: the Lax-Friedrichs speeds of stages 2 and 3
+                             are those of their own input states U^(1),
+                             U^(2) (dt still from U^n); 0: U^n's speeds in
+                             all three stages (the paper's, Sec. 2.1)      */
+    int32_t reserved_;    /* zero                                           */
 } hweno_config;
 
 enum { HWENO_BETA_MOMENT = 0, HWENO_BETA_CLASSICAL = 1 };
@@ -117,7 +122,7 @@ enum { HWENO_BETA_MOMENT = 0, HWENO_BETA_CLASSICAL = 1 };
 /* Fills cfg with the paper's settings for dimension dim: gamma = 1/400 per
  * linear polynomial and the rest on p0 (Sec. 3), eps = 1e-8, CFL 0.6, Q = 3,
  * W_BETA, F64, dt_exponent 1, component-wise reconstruction, the moment
- * smoothness indicator. */
+ * smoothness indicator, one set of speeds per step. */
 void hweno_default_config(int32_t dim, hweno_config* cfg);
 
 /* Bytes of device memory hweno_create needs for these problems, so that a

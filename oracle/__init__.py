@@ -46,7 +46,7 @@ class _Problem(C.Structure):
                 ("gas_gamma", C.c_double), ("adv", C.c_double * 2),
                 ("gauss_q", C.c_int), ("weights", C.c_int),
                 ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("charwise", C.c_int),
-                ("smoothness", C.c_int)]
+                ("smoothness", C.c_int), ("alpha_stage", C.c_int)]
 
 
 @dataclass
@@ -69,6 +69,7 @@ class Problem:
     eps: float = 1e-8
     charwise: int = 0
     smoothness: int = BETA_MOMENT
+    alpha_stage: int = 0
 
     def __post_init__(self):
         if self.gamma_lin is None:
@@ -103,7 +104,7 @@ class Problem:
                         self.ylo, self.yhi, self.bc_x, self.bc_y, self.gas_gamma,
                         (C.c_double * 2)(*self.adv), self.gauss_q, self.weights,
                         (C.c_double * 5)(*g), self.eps, int(self.charwise),
-                        int(self.smoothness))
+                        int(self.smoothness), int(self.alpha_stage))
 
 
 _lib = None

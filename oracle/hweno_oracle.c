@@ -1010,6 +1010,28 @@ static void window_refill(const orc_problem* p, ext_t* e, int i0, int j0, int gx
         }
 }
 
+/* Lax-Friedrichs speeds of an extended whole-grid state (interior cells);
+ * -2 if a cell is not admissible. */
+static int ext_alpha(const orc_problem* p, ext_t* e, int gx, int gy, double* ax, double* ay) {
+    int K = e->K;
+    double mx = 0.0, my = 0.0;
+    for (int j = gy; j < e->nye - gy; ++j)
+        for (int i = gx; i < e->nxe - gx; ++i) {
+            double U[4];
+            for (int c = 0; c < K; ++c) U[c] = ext_at(e, 0, c)[(size_t)j * e->nxe + i];
+            double s;
+            if (max_speed(p, 0, U, &s)) return -2;
+            if (s > mx) mx = s;
+            if (p->dim == 2) {
+                if (max_speed(p, 1, U, &s)) return -2;
+                if (s > my) my = s;
+            }
+        }
+    *ax = mx;
+    *ay = my;
+    return 0;
+}
+
 static int ssprk3_ext(const orc_problem* p, ext_t* E, double ax, double ay, double dt,
                       int gx, int gy, int refill, int i0, int j0) {
     int K = E->K, nv = E->nv, nxe = E->nxe, nye = E->nye;
@@ -1035,7 +1057,14 @@ static int ssprk3_ext(const orc_problem* p, ext_t* E, double ax, double ay, doub
     for (int s = 0; s < 3 && rc == 0; ++s) {
         ext_t* Us = stage_in[s];
         if (refill && s > 0) ghost_fill(p, Us, gx, gy);
-        rc = eval_operator(p, Us, ax, ay, xa[s], xb[s], ya[s], yb[s], &L, &Uh);
+        double sax = ax, say = ay;
+        if (p->alpha_stage && s > 0) {
+            /* speeds of this stage's input over the interior cells */
+            if (!refill) { rc = -1; break; }
+            rc = ext_alpha(p, Us, gx, gy, &sax, &say);
+            if (rc) break;
+        }
+        rc = eval_operator(p, Us, sax, say, xa[s], xb[s], ya[s], yb[s], &L, &Uh);
         if (rc) break;
         for (int v = 0; v < nv; ++v)
             for (int c = 0; c < K; ++c) {

@@ -49,6 +49,10 @@ typedef struct {
     int smoothness;        /* indicator of p0: ORC_BETA_MOMENT (the paper's,
                               eq. smoothness-indicator) or ORC_BETA_CLASSICAL
                               (eq. smoothness-indicator-typical, -2D) */
+    int alpha_stage;       /* 1: the Lax-Friedrichs speeds of stages 2 and 3
+                              come from their input states U^(1), U^(2)
+                              (whole-grid stepping only); 0: all three stages
+                              use those of U^n.  dt always uses U^n's. */
 } orc_problem;
 
 /* Number of conserved components K of the problem. */
@@ -121,7 +125,8 @@ double orc_dt(const orc_problem* p, double ax, double ay, double cfl, double dt_
 int orc_rhs(const orc_problem* p, const double* state, double ax, double ay,
             double* L_out, double* Uhat_out);
 
-/* One SSP-RK3 step with the derivative modification, in place. */
+/* One SSP-RK3 step with the derivative modification, in place.  Returns
+ * -2 if, with alpha_stage, an intermediate stage is not admissible. */
 int orc_step(const orc_problem* p, double* state, double ax, double ay, double dt);
 
 /* Advance from t0 to t_end: per step alpha from U^n, dt from the CFL rule,
@@ -130,7 +135,8 @@ int orc_run(const orc_problem* p, double* state, double t0, double t_end,
             double cfl, double dt_exponent, long long* steps_out);
 
 /* One SSP-RK3 step (given alpha and dt) evaluated only for the cells of the
- * window [i0,i0+wi) x [j0,j0+wj) of the full-grid state.  The result equals
+ * window [i0,i0+wi) x [j0,j0+wj) of the full-grid state (not with
+ * alpha_stage, whose speeds need the whole intermediate states: -1).  The result equals
  * the window of orc_step's result; out has the state layout of the window
  * (nx -> wi, ny -> wj).  Used to check single cells of very large grids. */
 int orc_step_window(const orc_problem* p, const double* state, double ax, double ay,

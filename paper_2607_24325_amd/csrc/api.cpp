@@ -145,6 +145,8 @@ static int validate(const hweno_problem* probs, int32_t nprob, const hweno_confi
         return fail(h, HWENO_ERR_ARG, "characteristic must be 0 or 1");
     if (cfg->smoothness != HWENO_BETA_MOMENT && cfg->smoothness != HWENO_BETA_CLASSICAL)
         return fail(h, HWENO_ERR_ARG, "unknown smoothness indicator %d", cfg->smoothness);
+    if (cfg->alpha_stage != 0 && cfg->alpha_stage != 1)
+        return fail(h, HWENO_ERR_ARG, "alpha_stage must be 0 or 1");
     return HWENO_OK;
 }
 
@@ -513,9 +515,9 @@ static hipError_t launch_stage(hweno_handle* h, int mode, const StageArgs& a) {
 }
 
 static int alpha_all(hweno_handle* h) {
-    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, 1, h->stream));
+    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, SEL_ALL, h->stream));
     HIP_TRY(h, launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
-                            h->nchunks, h->sch, 1, 0, h->stream));
+                            h->nchunks, h->sch, SEL_ALL, 0, h->stream));
     return HWENO_OK;
 }
 
@@ -567,17 +569,37 @@ extern "C" int hweno_rhs(hweno_handle* h, int32_t prob, double* L_out, double* U
 
 // One SSP-RK3 step of every unfinished problem: wave speeds and dt, three
 // fused stage kernels, time update.
-static int enqueue_step(hweno_handle* h, int use_dt_in) {
+// The launches of one step, in order; rec(kind, launch) issues each one
+// (and may bracket it with events).
+enum LaunchKind { LK_OTHER = 0, LK_ALPHA = 1, LK_STAGE = 2 };
+
+template <class Rec> static int enqueue_step_with(hweno_handle* h, int use_dt_in, Rec&& rec) {
     // speeds are gathered by stage 3 of the previous step; the reduction
     // kernel only fills them in after set_state
-    HIP_TRY(h, launch_reset(h->d_probs, h->d_ctl, h->nprob, 0, h->stream));
-    HIP_TRY(h, launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
-                            h->nchunks, h->sch, 0, 0, h->stream));
-    HIP_TRY(h, launch_dt(h->d_probs, h->d_ctl, h->nprob, use_dt_in, h->stream));
-    for (int mode = MODE_S1; mode <= MODE_S3; ++mode)
-        HIP_TRY(h, launch_stage(h, mode, stage_args(h, mode)));
-    HIP_TRY(h, launch_finish(h->d_probs, h->d_ctl, h->nprob, h->stream));
+    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_reset(h->d_probs, h->d_ctl, h->nprob, SEL_STALE, h->stream); }));
+    HIP_TRY(h, rec(LK_ALPHA, [&] {
+        return launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
+                            h->nchunks, h->sch, SEL_STALE, 0, h->stream);
+    }));
+    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_dt(h->d_probs, h->d_ctl, h->nprob, use_dt_in, h->stream); }));
+    for (int mode = MODE_S1; mode <= MODE_S3; ++mode) {
+        if (mode != MODE_S1 && h->cfg.alpha_stage) {
+            // speeds of this stage's input (per-stage option)
+            const void* uin = h->U[mode - 1].u;
+            HIP_TRY(h, rec(LK_OTHER, [&] { return launch_reset(h->d_probs, h->d_ctl, h->nprob, SEL_ACTIVE, h->stream); }));
+            HIP_TRY(h, rec(LK_ALPHA, [&] {
+                return launch_alpha(h->prec, h->flux, h->dim, uin, h->d_probs, h->d_chunks,
+                                    h->nchunks, h->sch, SEL_ACTIVE, 0, h->stream);
+            }));
+        }
+        HIP_TRY(h, rec(LK_STAGE, [&] { return launch_stage(h, mode, stage_args(h, mode)); }));
+    }
+    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_finish(h->d_probs, h->d_ctl, h->nprob, h->stream); }));
     return HWENO_OK;
+}
+
+static int enqueue_step(hweno_handle* h, int use_dt_in) {
+    return enqueue_step_with(h, use_dt_in, [](int, auto&& launch) { return launch(); });
 }
 
 static int launch_step(hweno_handle* h) {
@@ -758,54 +780,57 @@ extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* 
     int rc = all_set(h);
     if (rc) return rc;
     std::memset(out, 0, sizeof *out);
-    const int per_step = 7;
-    std::vector<hipEvent_t> ev(2 * per_step * (size_t)nsteps + 2);
-    for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
+    // an event pair around every launch of every step
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kinds;
+    auto fresh = [&]() -> hipEvent_t {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    };
     StepCtl c0{}, c1{};
     HIP_TRY(h, hipMemcpyAsync(&c0, h->d_ctl, sizeof c0, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    size_t k = 0;
-    HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-    const size_t first = 1;
-    for (int s = 0; s < nsteps; ++s) {
-        auto rec = [&](hipError_t launched) -> hipError_t {
-            if (launched != hipSuccess) return launched;
-            return hipEventRecord(ev[k++], h->stream);
-        };
-        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-        HIP_TRY(h, rec(launch_reset(h->d_probs, h->d_ctl, h->nprob, 0, h->stream)));
-        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-        HIP_TRY(h, rec(launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs,
-                                    h->d_chunks, h->nchunks, h->sch, 0, 0, h->stream)));
-        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-        HIP_TRY(h, rec(launch_dt(h->d_probs, h->d_ctl, h->nprob, 0, h->stream)));
-        for (int mode = MODE_S1; mode <= MODE_S3; ++mode) {
-            HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-            HIP_TRY(h, rec(launch_stage(h, mode, stage_args(h, mode))));
-        }
-        HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-        HIP_TRY(h, rec(launch_finish(h->d_probs, h->d_ctl, h->nprob, h->stream)));
+    hipEvent_t start = fresh();
+    if (!start) return fail(h, HWENO_ERR_HIP, "event creation failed");
+    HIP_TRY(h, hipEventRecord(start, h->stream));
+    for (int s = 0; s < nsteps && rc == HWENO_OK; ++s) {
+        rc = enqueue_step_with(h, 0, [&](int kind, auto&& launch) -> hipError_t {
+            hipEvent_t a = fresh(), b = fresh();
+            if (!a || !b) return hipErrorOutOfMemory;
+            hipError_t e = hipEventRecord(a, h->stream);
+            if (e != hipSuccess) return e;
+            e = launch();
+            if (e != hipSuccess) return e;
+            kinds.push_back(kind);
+            return hipEventRecord(b, h->stream);
+        });
     }
-    HIP_TRY(h, hipEventRecord(ev[k++], h->stream));
-    HIP_TRY(h, hipEventSynchronize(ev[k - 1]));
-    float ms = 0.f;
-    HIP_TRY(h, hipEventElapsedTime(&ms, ev[0], ev[k - 1]));
-    out->total_ms = ms;
-    // pairs in launch order: reset, alpha, dt, stage x3, finish
-    size_t e = first;
-    for (int s = 0; s < nsteps; ++s)
-        for (int j = 0; j < per_step; ++j, e += 2) {
-            HIP_TRY(h, hipEventElapsedTime(&ms, ev[e], ev[e + 1]));
-            if (j >= 3 && j <= 5) {
+    hipEvent_t stop = rc == HWENO_OK ? fresh() : nullptr;
+    if (stop) {
+        HIP_TRY(h, hipEventRecord(stop, h->stream));
+        HIP_TRY(h, hipEventSynchronize(stop));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, start, stop));
+        out->total_ms = ms;
+        for (size_t i = 0; i < kinds.size(); ++i) {
+            HIP_TRY(h, hipEventElapsedTime(&ms, ev[1 + 2 * i], ev[2 + 2 * i]));
+            if (kinds[i] == LK_STAGE) {
                 out->stage_ms += ms;
                 out->stage_launches += 1;
-            } else if (j == 1) {
+            } else if (kinds[i] == LK_ALPHA) {
                 out->alpha_ms += ms;
             } else {
                 out->other_ms += ms;
             }
         }
+    } else if (rc == HWENO_OK) {
+        rc = fail(h, HWENO_ERR_HIP, "event creation failed");
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (auto& x : ev) hipEventDestroy(x);
+    if (rc) return rc;
     HIP_TRY(h, hipMemcpyAsync(&c1, h->d_ctl, sizeof c1, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     out->steps = c1.steps - c0.steps;

@@ -5,15 +5,20 @@
 
 namespace hweno {
 
-// Zeroes the wave-speed maxima that are about to be recomputed (all of
-// them, or those not current) and the step counters.
-__global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems) {
+// Zeroes the wave-speed maxima that are about to be recomputed (SpeedSel)
+// and, at the start of a step, the step counters.
+__global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int sel) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < nprob && (all_problems || !probs[p].alpha_valid)) {
-        probs[p].ax_bits = 0;
-        probs[p].ay_bits = 0;
+    if (p < nprob) {
+        const ProbDev& P_ = probs[p];
+        const bool pick = sel == SEL_ALL || (sel == SEL_STALE && !P_.alpha_valid) ||
+                          (sel == SEL_ACTIVE && P_.active && !(P_.err & ERR_STAGE_BAD));
+        if (pick) {
+            probs[p].ax_bits = 0;
+            probs[p].ay_bits = 0;
+        }
     }
-    if (p == 0) {
+    if (p == 0 && sel != SEL_ACTIVE) {
         ctl->nactive = 0;
         ctl->step_active = 0;
     }
@@ -25,7 +30,7 @@ __global__ void reset_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int all_pr
 template <int P, int FLUX, int DIM>
 __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* probs,
                                                     const Chunk* chunks, int nchunks,
-                                                    Scheme sch, int all_problems) {
+                                                    Scheme sch, int sel) {
     using TU = typename PrecT<P>::TU;
     constexpr int K = FLUX == F_EULER ? (DIM == 1 ? 3 : 4) : 1;
     __shared__ double smx[4], smy[4];
@@ -34,7 +39,8 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const Chunk chunk = chunks[ch];
         ProbDev& P_ = probs[chunk.prob];
-        if (!all_problems && (!(P_.t < P_.t_end) || P_.err || P_.alpha_valid)) continue;
+        if (sel == SEL_STALE && (!(P_.t < P_.t_end) || P_.err || P_.alpha_valid)) continue;
+        if (sel == SEL_ACTIVE && (!P_.active || (P_.err & ERR_STAGE_BAD))) continue;
         const int64_t plane = (int64_t)P_.nx * P_.ny;
         const TU* base = U + P_.off_u;
         double mx = 0.0, my = 0.0;
@@ -85,7 +91,7 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
             atomicMax((unsigned long long*)&P_.ay_bits, (unsigned long long)__double_as_longlong(my));
             if (bad != LLONG_MAX) {
                 atomicMin((long long*)&P_.bad_cell, bad);
-                atomicOr(&P_.err, 1);
+                atomicOr(&P_.err, sel == SEL_ACTIVE ? ERR_STAGE_BAD : ERR_STATE_BAD);
             }
         }
         __syncthreads();
@@ -125,7 +131,9 @@ __global__ void finish_kernel(ProbDev* probs, StepCtl* ctl, int nprob) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < nprob) {
         ProbDev& P_ = probs[p];
-        if (P_.active) {
+        // a problem whose intermediate stage was not admissible skipped its
+        // stages 2 and 3: its state and time stay those of U^n
+        if (P_.active && !(P_.err & ERR_STAGE_BAD)) {
             P_.t = P_.last ? P_.t_end : P_.t + P_.dt;
             P_.ax_bits = P_.ax_next;
             P_.ay_bits = P_.ay_next;
@@ -159,34 +167,34 @@ __global__ void pack_kernel(int to_internal, double* ext, TU* u, TD* d, int K, i
 
 // --------------------------------------------------------------- launchers
 
-hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems, hipStream_t s) {
-    reset_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, all_problems);
+hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int sel, hipStream_t s) {
+    reset_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, sel);
     return hipGetLastError();
 }
 
 template <int P>
 static hipError_t alpha_dispatch(int flux, int dim, const void* u, ProbDev* probs,
-                                 const Chunk* chunks, int nchunks, const Scheme& sch, int all,
+                                 const Chunk* chunks, int nchunks, const Scheme& sch, int sel,
                                  int grid, hipStream_t s) {
     if (dim == 1) {
-        if (flux == F_ADV) alpha_kernel<P, F_ADV, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
-        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
-        else alpha_kernel<P, F_EULER, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        if (flux == F_ADV) alpha_kernel<P, F_ADV, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
+        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
+        else alpha_kernel<P, F_EULER, 1><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
     } else {
-        if (flux == F_ADV) alpha_kernel<P, F_ADV, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
-        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
-        else alpha_kernel<P, F_EULER, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, all);
+        if (flux == F_ADV) alpha_kernel<P, F_ADV, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
+        else if (flux == F_BURGERS) alpha_kernel<P, F_BURGERS, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
+        else alpha_kernel<P, F_EULER, 2><<<grid, 256, 0, s>>>(u, probs, chunks, nchunks, sch, sel);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* probs,
-                        const Chunk* chunks, int nchunks, const Scheme& sch, int all_problems,
+                        const Chunk* chunks, int nchunks, const Scheme& sch, int sel,
                         int grid, hipStream_t s) {
     if (grid <= 0 || grid > nchunks) grid = nchunks;
-    if (prec == P_F32) return alpha_dispatch<P_F32>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
-    if (prec == P_KAHAN) return alpha_dispatch<P_KAHAN>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
-    return alpha_dispatch<P_F64>(flux, dim, u, probs, chunks, nchunks, sch, all_problems, grid, s);
+    if (prec == P_F32) return alpha_dispatch<P_F32>(flux, dim, u, probs, chunks, nchunks, sch, sel, grid, s);
+    if (prec == P_KAHAN) return alpha_dispatch<P_KAHAN>(flux, dim, u, probs, chunks, nchunks, sch, sel, grid, s);
+    return alpha_dispatch<P_F64>(flux, dim, u, probs, chunks, nchunks, sch, sel, grid, s);
 }
 
 hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, hipStream_t s) {

@@ -243,7 +243,7 @@ __device__ __forceinline__ void publish_reduced(ProbDev& P, double mx, double my
         atomicMax((unsigned long long*)&P.ay_next, (unsigned long long)__double_as_longlong(my));
     if (bad != LLONG_MAX) {
         atomicMin((long long*)&P.bad_cell, bad);
-        atomicOr(&P.err, 1);
+        atomicOr(&P.err, ERR_STATE_BAD);
     }
 }
 

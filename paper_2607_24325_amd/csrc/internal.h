@@ -37,7 +37,8 @@ struct ProbDev {
     uint64_t ay_next;
     int32_t active;    // 1 while the current step advances this problem
     int32_t last;      // the current step lands exactly on t_end
-    int32_t err;       // non-admissible state seen
+    int32_t err;       // non-admissible state seen: ERR_STATE_BAD (a stored state),
+                       // ERR_STAGE_BAD (an intermediate stage input)
     int32_t alpha_valid;  // ax_bits/ay_bits hold the speeds of the current state
     int64_t bad_cell;  // smallest flat index of a non-admissible cell
 };
@@ -113,12 +114,17 @@ hipError_t launch_stage2d(int prec, int flux, int Q, int mode, const StageArgs& 
                           hipStream_t s);
 // all_problems: zero the speeds of every problem (queries), or only of those
 // whose speeds are not current (time stepping).
-hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int all_problems, hipStream_t s);
+// Which problems a speed reset / reduction covers: every problem (after
+// set_state), those whose speeds are not current (step start), or those
+// active in the step (the per-stage speeds of stages 2 and 3).
+enum SpeedSel : int { SEL_STALE = 0, SEL_ALL = 1, SEL_ACTIVE = 2 };
+constexpr int ERR_STATE_BAD = 1, ERR_STAGE_BAD = 2;
+hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int sel, hipStream_t s);
 // all_problems: 1 = every problem (rhs / alpha queries); 0 = only problems
 // still short of t_end, without a pending error and whose speeds are not
 // current (time stepping: stage 3 computes them for the next step).
 hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* probs,
-                        const Chunk* chunks, int nchunks, const Scheme& sch, int all_problems,
+                        const Chunk* chunks, int nchunks, const Scheme& sch, int sel,
                         int grid, hipStream_t s);
 hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, hipStream_t s);
 hipError_t launch_finish(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s);

@@ -40,7 +40,11 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
         const Tile1D tile = tiles[tix];
         const ProbDev& P_ = a.probs[tile.prob];
-        if (mode != MODE_RHS && !P_.active) continue;
+        // stages 2 and 3 skip a problem whose stage input was not admissible
+        // (per-stage speeds): its U^n stays as it is
+        if (mode != MODE_RHS &&
+            (!P_.active || (mode != MODE_S1 && (P_.err & ERR_STAGE_BAD))))
+            continue;
         const int nx = P_.nx, bcx = P_.bc_x;
         const T dx = (T)P_.dx, inv_dx = (T)P_.inv_dx;
         const TA inv_dx_a = (TA)P_.inv_dx;

@@ -61,7 +61,11 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
     for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
         const Tile2D tile = tiles[tix];
         const ProbDev& P_ = a.probs[tile.prob];
-        if (mode != MODE_RHS && !P_.active) continue;
+        // stages 2 and 3 skip a problem whose stage input was not admissible
+        // (per-stage speeds): its U^n stays as it is
+        if (mode != MODE_RHS &&
+            (!P_.active || (mode != MODE_S1 && (P_.err & ERR_STAGE_BAD))))
+            continue;
         const int nx = P_.nx, ny = P_.ny, bcx = P_.bc_x, bcy = P_.bc_y;
         const int64_t plane = (int64_t)nx * ny;
         const T inv_dx = (T)P_.inv_dx, inv_dy = (T)P_.inv_dy;

@@ -36,7 +36,8 @@ class hweno_config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("gauss_q", C.c_int32), ("weights", C.c_int32),
                 ("gamma_lin", C.c_double * 5), ("eps", C.c_double), ("cfl", C.c_double),
                 ("dt_exponent", C.c_double), ("characteristic", C.c_int32),
-                ("smoothness", C.c_int32)]
+                ("smoothness", C.c_int32), ("alpha_stage", C.c_int32),
+                ("reserved_", C.c_int32)]
 
 
 class hweno_tuning(C.Structure):

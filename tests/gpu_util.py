@@ -12,7 +12,7 @@ def oproblem(spec, cfg):
                      gas_gamma=spec.gas_gamma, adv=tuple(spec.adv), gauss_q=cfg.gauss_q,
                      weights=cfg.weights, gamma_lin=tuple(cfg.gamma_lin)[:3 if spec.dim == 1 else 5],
                      eps=cfg.eps, charwise=int(cfg.characteristic),
-                     smoothness=int(cfg.smoothness))
+                     smoothness=int(cfg.smoothness), alpha_stage=int(cfg.alpha_stage))
 
 
 def plane_rel(gpu, ref):

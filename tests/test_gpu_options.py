@@ -120,3 +120,79 @@ def test_q3_batched_uneven_problems(prec):
             assert ok, (spec.name, err, bar)
         else:
             assert l1_rel(g[0], ref[0]) < 2e-5, (spec.name, l1_rel(g[0], ref[0]))
+
+
+# ------------------------------------------------------- per-stage speeds --
+
+CASES_STAGE = {
+    "riemann-1d-600": lambda: W.riemann_1d(3, nx=600),
+    "blast-1d-800": lambda: W.blast_1d(800),
+    "quadrant-vortex-2d-96": lambda: W.quadrant_vortex_2d(96, seed=7),
+}
+
+
+@pytest.mark.parametrize("charwise", [0, 1])
+@pytest.mark.parametrize("case", list(CASES_STAGE))
+def test_per_stage_speeds_step(case, charwise):
+    """stages 2 and 3 take their Lax-Friedrichs speeds from U^(1), U^(2):
+    two steps against the oracle (the second from the state the first left)"""
+    spec, st = CASES_STAGE[case]()
+    cfg = hw.default_config(spec.dim, precision=hw.F64, gauss_q=2, characteristic=charwise,
+                            alpha_stage=1)
+    p = oproblem(spec, cfg)
+    assert p.alpha_stage == 1
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        cur = st
+        for _ in range(2):
+            dt = h.step(want_dt=True)[0]
+            gpu, _ = h.get_state(0)
+            ax, ay = O.alpha(p, cur)
+            ay = ay if spec.dim == 2 else 0.0
+            assert abs(dt - O.dt(p, ax, ay, cfg.cfl)) <= 1e-14 * dt
+            fn = lambda s: O.step(p, s, ax, ay, dt)   # noqa: E731
+            S = natural_scales(spec, cur)
+            ok, err, bar = within_conditioning(gpu, fn(cur), S, oracle_sensitivity(fn, cur, S),
+                                               1e-12)
+            assert ok, (err, bar)
+            cur = gpu
+    # the option changes the result on these data
+    p0 = oproblem(spec, hw.default_config(spec.dim, precision=hw.F64, gauss_q=2,
+                                          characteristic=charwise))
+    ax, ay = O.alpha(p0, st)
+    ay = ay if spec.dim == 2 else 0.0
+    dt0 = O.dt(p0, ax, ay, cfg.cfl)
+    assert np.abs(O.step(p0, st, ax, ay, dt0) - O.step(p, st, ax, ay, dt0)).max() > 0
+
+
+def test_per_stage_speeds_reduced_precision_and_timing():
+    spec, st = W.quadrant_vortex_2d(96, seed=7)
+    cfg = hw.default_config(2, precision=hw.F32_ACC64, gauss_q=2, alpha_stage=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dts = [h.step(want_dt=True)[0] for _ in range(3)]
+        gpu, _ = h.get_state(0)
+        tm = h.timed_steps(2)
+        assert tm.steps == 2 and tm.stage_launches == 6 and tm.alpha_ms > 0
+    p = oproblem(spec, cfg)
+    ref = st
+    for dt in dts:
+        ax, ay = O.alpha(p, ref)
+        ref = O.step(p, ref, ax, ay, dt)
+    assert l1_rel(gpu[0], ref[0]) < 2e-5, l1_rel(gpu[0], ref[0])
+
+
+def test_per_stage_speeds_lax_run():
+    spec, st = W.lax_1d(400)
+    cfg = hw.default_config(1, precision=hw.F64, characteristic=1, alpha_stage=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        steps = h.run_to_time()
+        gpu, t = h.get_state(0)
+    p = oproblem(spec, cfg)
+    ref, n = O.run(p, st, 0.0, 0.16, cfg.cfl)
+    assert steps == n and t == 0.16
+    S = natural_scales(spec, st)
+    sens = oracle_sensitivity(lambda s: O.run(p, s, 0.0, 0.16, cfg.cfl)[0], st, S)
+    ok, err, bar = within_conditioning(gpu, ref, S, sens, 1e-10)
+    assert ok, (err, bar)
