@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import oproblem, natural_scales, scaled_err
+from gpu_util import oproblem, natural_scales, scaled_err, scaled_err_planes
 from paper_2607_24325_amd import hweno as hw
 from paper_2607_24325_amd import workloads as W
 
@@ -80,3 +80,36 @@ def test_full_run_256_to_final_time():
     assert steps == n and t == 0.1
     assert np.abs(out[0] - ref[0]).mean() <= 1e-10
     assert scaled_err(out, ref, natural_scales(spec, st)) < 1e-9
+
+
+@pytest.mark.parametrize("prec,floor", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-5)])
+def test_fullsize_characteristic_step_sampled(workload, prec, floor):
+    """The characteristic-variable path at the full size, in the launch
+    configuration the benchmark times: one step on the sampled windows, plane
+    by plane at `floor` of the natural scales or 10x the oracle's own
+    sensitivity to 1e-15 input perturbations where that is larger (the
+    projection with |L| |R| >> 1 amplifies rounding in low-sound-speed
+    cells)."""
+    spec, st = workload
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5, characteristic=1)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dt = h.step(want_dt=True)[0]
+        out, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    assert p.charwise == 1
+    O.set_threads(os.cpu_count() or 1)
+    ax, ay = O.alpha(p, st)
+    S = natural_scales(spec, st)
+    rng = np.random.default_rng(0)
+    perturbed = [st * (1.0 + 1e-15 * rng.standard_normal(st.shape)) for _ in range(2)]
+    for (i0, j0, wi, wj) in windows(N):
+        ref = O.step_window(p, st, ax, ay, dt, i0, j0, wi, wj)
+        sens = None
+        for sp in perturbed:
+            e = scaled_err_planes(O.step_window(p, sp, ax, ay, dt, i0, j0, wi, wj), ref, S)
+            sens = e if sens is None else np.maximum(sens, e)
+        got = out[:, :, j0:j0 + wj, i0:i0 + wi]
+        err = scaled_err_planes(got, ref, S)
+        bar = np.maximum(floor, 10.0 * sens)
+        assert np.all(err <= bar), (i0, j0, err.max(), bar.min())

@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 import bruteforce as BF
+from exact_burgers import burgers1d_exact_avg, burgers2d_exact_avg
 from paper_2607_24325_amd import workloads as W
 
 RNG = np.random.default_rng(2024)
@@ -234,20 +235,6 @@ def test_advection_headline_case_with_cfl_time_step():
 
 # ------------------------------------------------------- paper tables -----
 
-def _burgers_exact_avg(nx, t, nq=10):
-    dx = 2.0 / nx
-    g, w = np.polynomial.legendre.leggauss(nq)
-    g, w = 0.5 * (g + 1), 0.5 * w
-    avg = np.zeros(nx)
-    for gq, wq in zip(g, w):
-        x = dx * (np.arange(nx) + gq)
-        xi = x.copy()
-        for _ in range(80):   # characteristics: x = xi + u0(xi) t
-            xi -= (xi + (0.5 + np.sin(np.pi * xi)) * t - x) / (1 + np.pi * np.cos(np.pi * xi) * t)
-        avg += wq * (0.5 + np.sin(np.pi * xi))
-    return avg
-
-
 TABLE1 = {40: (2.66e-05, 1.39e-04), 80: (3.65e-07, 4.32e-06), 120: (4.64e-08, 6.02e-07),
           160: (1.08e-08, 1.44e-07), 200: (3.57e-09, 4.72e-08), 240: (1.44e-09, 1.90e-08)}
 
@@ -261,7 +248,7 @@ def test_table1_burgers_1d():
         spec, st = W.burgers_1d(n)
         p = oproblem(spec)
         out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
-        e = np.abs(out[0, 0, 0] - _burgers_exact_avg(n, spec.t_end))
+        e = np.abs(out[0, 0, 0] - burgers1d_exact_avg(n, spec.t_end))
         res[n] = (e.mean(), e.max())
     for n in (80, 120, 160, 200, 240):
         for k in (0, 1):
@@ -279,7 +266,7 @@ def test_table1_rejects_first_order_time_step():
     spec, st = W.burgers_1d(240)
     p = oproblem(spec)
     out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 1.0)
-    e = np.abs(out[0, 0, 0] - _burgers_exact_avg(240, spec.t_end)).mean()
+    e = np.abs(out[0, 0, 0] - burgers1d_exact_avg(240, spec.t_end)).mean()
     assert e > 50 * TABLE1[240][0]
 
 
@@ -300,23 +287,6 @@ def test_table2_euler_1d_weak():
         assert 0.9 < e / l1 < 1.1, (n, e, l1)
 
 
-def _burgers2d_exact_avg(n, t, nq=6):
-    dx = 4.0 / n
-    g, w = np.polynomial.legendre.leggauss(nq)
-    g, w = 0.5 * (g + 1), 0.5 * w
-    J, I = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    avg = np.zeros((n, n))
-    for a in range(nq):
-        for b in range(nq):
-            s = (I + g[a]) * dx + (J + g[b]) * dx
-            xi = s.copy()
-            for _ in range(60):   # u = u0(s - 2 u t), s = x + y
-                xi -= (xi + 2 * (0.5 + np.sin(0.5 * np.pi * xi)) * t - s) / \
-                      (1 + np.pi * np.cos(0.5 * np.pi * xi) * t)
-            avg += w[a] * w[b] * (0.5 + np.sin(0.5 * np.pi * xi))
-    return avg
-
-
 TABLE3 = {40: (3.87e-05, 2.51e-04), 80: (1.13e-06, 1.33e-05)}
 
 
@@ -330,12 +300,12 @@ def test_table3_burgers_2d_selects_the_weight_form():
             spec, st = W.burgers_2d(n)
             p = oproblem(spec, gauss_q=3, weights=O.W_BETA)
             out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
-            e = np.abs(out[0, 0] - _burgers2d_exact_avg(n, spec.t_end))
+            e = np.abs(out[0, 0] - burgers2d_exact_avg(n, spec.t_end))
             assert 0.9 < e.mean() / l1 < 1.1 and 0.9 < e.max() / li < 1.1, (n, e.mean(), e.max())
         spec, st = W.burgers_2d(40)
         p = oproblem(spec, gauss_q=3, weights=O.W_BETA2)
         out, _ = O.run(p, st, 0.0, spec.t_end, 0.6, 5.0 / 3.0)
-        e = np.abs(out[0, 0] - _burgers2d_exact_avg(40, spec.t_end))
+        e = np.abs(out[0, 0] - burgers2d_exact_avg(40, spec.t_end))
         assert e.mean() > 10 * TABLE3[40][0]
     finally:
         O.set_threads(0)
