@@ -10,7 +10,8 @@
 // adjacent lanes and the rows below/above stay in registers as the march
 // advances.  Per row:
 //   R  each (lane, component) reconstructs its cell and writes the values of
-//      U, u_x, u_y at the Gauss points of its four faces to LDS;
+//      U, u_xi, u_eta (local units) at the Gauss points of its four faces to
+//      LDS;
 //   F  each thread computes the Lax-Friedrichs flux (all components) at one
 //      edge Gauss point: the x-edges of this row and the y-edges between this
 //      row and the one below;
@@ -159,7 +160,10 @@ template <class T> __device__ __forceinline__ void transpose15(const T* C, T* D)
     D[12] = C[12]; D[13] = C[11]; D[14] = C[10];
 }
 
-// Lax-Friedrichs flux at one edge point, all components: out = (f, f^v, f^w).
+// Lax-Friedrichs flux at one edge point, all components, TWICE its value:
+// out = 2 (f, f^v, f^w) = (f(L) + f(R)) - alpha (R - L).  The factor 1/2 is
+// folded into the Gauss weights of the residual, which saves one multiply per
+// output (halving and doubling are exact in binary floating point).
 template <class T, int FLUX, int K, int DIR>
 __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T* UL, const T* VL,
                                         const T* WL, const T* UR, const T* VR, const T* WR,
@@ -167,12 +171,11 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
     T fL[K], fvL[K], fwL[K], fR[K], fvR[K], fwR[K];
     F.side(UL, VL, WL, fL, fvL, fwL);
     F.side(UR, VR, WR, fR, fvR, fwR);
-    const T ha = (T)0.5 * alpha;
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        out[c] = (T)0.5 * (fL[c] + fR[c]) - ha * (UR[c] - UL[c]);
-        out[K + c] = (T)0.5 * (fvL[c] + fvR[c]) - ha * (VR[c] - VL[c]);
-        out[2 * K + c] = (T)0.5 * (fwL[c] + fwR[c]) - ha * (WR[c] - WL[c]);
+        out[c] = (fL[c] + fR[c]) - alpha * (UR[c] - UL[c]);
+        out[K + c] = (fvL[c] + fvR[c]) - alpha * (VR[c] - VL[c]);
+        out[2 * K + c] = (fwL[c] + fwR[c]) - alpha * (WR[c] - WL[c]);
     }
 }
 
@@ -196,6 +199,22 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
     const Flux<T, FLUX, K, 0> FXf(sch);
     const Flux<T, FLUX, K, 1> FYf(sch);
     const Tile2D* tiles = (const Tile2D*)a.tiles + a.tile_offset;
+
+    // Stage 3 also gathers the wave speeds of the state it writes (for the
+    // next step's flux and time step): one wave per output row reads the four
+    // new averages of each cell from LDS one barrier after they were written
+    // and keeps per-lane maxima in LDS (no registers live across the march).
+    // The gathering wave rotates with the row: wave w of every resident
+    // workgroup runs on SIMD w, so a fixed wave would load one SIMD of the CU
+    // with all the gathers.  The maxima start cleared; the wave that
+    // publishes a tile's maxima clears them again for the next tile (ordered
+    // before that tile's first gather by its first barrier).
+    constexpr bool fuse_alpha = mode == MODE_S3;
+    if (fuse_alpha && c == 0) {
+        smx[lane] = 0.0;
+        smy[lane] = 0.0;
+        sbad[lane] = LLONG_MAX;
+    }
 
     for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
         const Tile2D tile = tiles[tix];
@@ -248,18 +267,9 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
         };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
 
-        // Stage 3 also gathers the wave speeds of the state it writes (for the
-        // next step's flux and time step): wave 0 reads the four new averages of
-        // each output cell from LDS one barrier after they were written and
-        // keeps per-lane maxima in LDS (no registers live across the march).
-        constexpr bool fuse_alpha = mode == MODE_S3;
-        if (fuse_alpha && c == 0) {
-            smx[lane] = 0.0;
-            smy[lane] = 0.0;
-            sbad[lane] = LLONG_MAX;
-        }
+        auto gather_wave = [](int row) { return (int)((unsigned)row % (unsigned)K); };
         auto gather_speeds = [&](int row) {
-            if (c == 0 && out_col) {
+            if (c == gather_wave(row) && out_col) {
                 double u[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) u[k] = snew[k][lane];
@@ -333,15 +343,18 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
             const T ucT = (T)u0;
             {
                 T val[2][Q], dn[2][Q], dtg[2][Q];
+                // Derivatives go to the faces in local units (d/dxi, d/deta): the
+                // edge flux is linear in them, so the 1/dx, 1/dy of u_x, u_y are
+                // applied once to the residual instead of at every face point.
                 face_values<T, Q>(C, val, dn, dtg);   // x-faces: dn = d/dxi, dt = d/deta
 #pragma unroll
                 for (int mu = 0; mu < Q; ++mu) {
                     sxL[(mu * 3 + 0) * K + c][lane] = ucT + val[0][mu];
-                    sxL[(mu * 3 + 1) * K + c][lane] = dn[0][mu] * inv_dx;
-                    sxL[(mu * 3 + 2) * K + c][lane] = dtg[0][mu] * inv_dy;
+                    sxL[(mu * 3 + 1) * K + c][lane] = dn[0][mu];
+                    sxL[(mu * 3 + 2) * K + c][lane] = dtg[0][mu];
                     sxR[(mu * 3 + 0) * K + c][lane] = ucT + val[1][mu];
-                    sxR[(mu * 3 + 1) * K + c][lane] = dn[1][mu] * inv_dx;
-                    sxR[(mu * 3 + 2) * K + c][lane] = dtg[1][mu] * inv_dy;
+                    sxR[(mu * 3 + 1) * K + c][lane] = dn[1][mu];
+                    sxR[(mu * 3 + 2) * K + c][lane] = dtg[1][mu];
                 }
                 T D[15];
                 transpose15(C, D);
@@ -349,11 +362,11 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
 #pragma unroll
                 for (int mu = 0; mu < Q; ++mu) {
                     syB[(mu * 3 + 0) * K + c][lane] = ucT + val[0][mu];
-                    syB[(mu * 3 + 1) * K + c][lane] = dtg[0][mu] * inv_dx;
-                    syB[(mu * 3 + 2) * K + c][lane] = dn[0][mu] * inv_dy;
+                    syB[(mu * 3 + 1) * K + c][lane] = dtg[0][mu];
+                    syB[(mu * 3 + 2) * K + c][lane] = dn[0][mu];
                     ytop[mu][0] = ucT + val[1][mu];
-                    ytop[mu][1] = dtg[1][mu] * inv_dx;
-                    ytop[mu][2] = dn[1][mu] * inv_dy;
+                    ytop[mu][1] = dtg[1][mu];
+                    ytop[mu][2] = dn[1][mu];
                 }
             }
 
@@ -404,7 +417,7 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                     T fr = 0, fl = 0, g = 0;
 #pragma unroll
                     for (int mu = 0; mu < Q; ++mu) {
-                        const T w = (T)Gauss<Q>::w(mu);
+                        const T w = (T)(0.5 * Gauss<Q>::w(mu));   // fluxes are stored doubled
                         fr += w * sFX[mu][sk * K + c][lane];
                         fl += w * sFX[mu][sk * K + c][lane > 0 ? lane - 1 : 0];
                         g += w * sFY[mu][sk * K + c][lane];
@@ -414,8 +427,9 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                 }
                 if (r > j0) {
                     const TA Lu = -(xd_prev[0] * inv_dx_a + (gy[0] - gy_prev[0]) * inv_dy_a);
-                    const T Lv = -((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
-                    const T Lw = -(ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
+                    // v- and w-fluxes carry the derivatives in local units
+                    const T Lv = -inv_dx * ((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
+                    const T Lw = -inv_dy * (ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
                     if (emit) {
                         const TA ucur = (TA)um;   // u-bar of row r-1 in the input set
                         if (mode == MODE_RHS) {
@@ -468,7 +482,14 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
         __syncthreads();  // LDS reuse by the next tile
         if (fuse_alpha) {
             gather_speeds(jend - 1);
-            if (c == 0) publish_next_speeds(a.probs[tile.prob], smx[lane], smy[lane], sbad[lane]);
+            if (c == gather_wave(jend - 1)) {
+                const double mxl = smx[lane], myl = smy[lane];
+                const long long badl = sbad[lane];
+                smx[lane] = 0.0;
+                smy[lane] = 0.0;
+                sbad[lane] = LLONG_MAX;
+                publish_next_speeds(a.probs[tile.prob], mxl, myl, badl);
+            }
         }
     }
 }

@@ -58,6 +58,13 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
     // y-direction component order (rho, m_y, m_x, E) -> storage index
     constexpr int PY[4] = {0, 2, 1, 3};
 
+    constexpr bool fuse_alpha = mode == MODE_S3;
+    if (fuse_alpha && c == 0) {   // ordered before the first gather by a barrier
+        smx[lane] = 0.0;
+        smy[lane] = 0.0;
+        sbad[lane] = LLONG_MAX;
+    }
+
     for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
         const Tile2D tile = tiles[tix];
         const ProbDev& P_ = a.probs[tile.prob];
@@ -104,14 +111,12 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
         };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;
 
-        constexpr bool fuse_alpha = mode == MODE_S3;
-        if (fuse_alpha && c == 0) {
-            smx[lane] = 0.0;
-            smy[lane] = 0.0;
-            sbad[lane] = LLONG_MAX;
-        }
-        auto gather_speeds = [&](int row) {
-            if (c == 0 && out_col) {
+        // row `row`'s speeds are gathered by wave w (rotating with the row in
+        // the march, so that the gathers spread over the SIMDs; per-lane
+        // maxima in LDS, cleared by the wave that publishes them)
+        auto gather_wave = [](int row) { return (int)((unsigned)row % (unsigned)K); };
+        auto gather_speeds = [&](int row, int w) {
+            if (c == w && out_col) {
                 double u[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) u[k] = snew[row & 1][k][lane];
@@ -148,7 +153,7 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
         const int lm = lane > 0 ? lane - 1 : 0, lp = lane < 63 ? lane + 1 : 63;
 
         for (int r = j0 - 1; r <= jend; ++r) {
-            if (fuse_alpha && r - 3 >= j0) gather_speeds(r - 3);
+            if (fuse_alpha && r - 3 >= j0) gather_speeds(r - 3, gather_wave(r - 3));
             // ring: row r+2 into the slot of row r-2; prefetch row r+3
             const TU u2 = un_;
             put_row(r + 2, un_, vn_, wn_);
@@ -232,16 +237,19 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
                 T C[15], vh, wh;
                 reconstruct2d<T>(wx, sch, squared, C, vh, wh);
                 vhx = vh;
+                // derivatives in local units (d/dxi, d/deta): the back
+                // projection and the edge flux are linear in them, and the
+                // residual applies 1/dx, 1/dy once
                 T val[2][Q], dn[2][Q], dtg[2][Q];
                 face_values<T, Q>(C, val, dn, dtg);
 #pragma unroll
                 for (int mu = 0; mu < Q; ++mu) {
                     sxL[(mu * 3 + 0) * K + c][lane] = val[0][mu];
-                    sxL[(mu * 3 + 1) * K + c][lane] = dn[0][mu] * inv_dx;
-                    sxL[(mu * 3 + 2) * K + c][lane] = dtg[0][mu] * inv_dy;
+                    sxL[(mu * 3 + 1) * K + c][lane] = dn[0][mu];
+                    sxL[(mu * 3 + 2) * K + c][lane] = dtg[0][mu];
                     sxR[(mu * 3 + 0) * K + c][lane] = val[1][mu];
-                    sxR[(mu * 3 + 1) * K + c][lane] = dn[1][mu] * inv_dx;
-                    sxR[(mu * 3 + 2) * K + c][lane] = dtg[1][mu] * inv_dy;
+                    sxR[(mu * 3 + 1) * K + c][lane] = dn[1][mu];
+                    sxR[(mu * 3 + 2) * K + c][lane] = dtg[1][mu];
                 }
             }
             {
@@ -255,11 +263,11 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
 #pragma unroll
                 for (int mu = 0; mu < Q; ++mu) {
                     syB[(mu * 3 + 0) * K + c][lane] = val[0][mu];
-                    syB[(mu * 3 + 1) * K + c][lane] = dtg[0][mu] * inv_dx;
-                    syB[(mu * 3 + 2) * K + c][lane] = dn[0][mu] * inv_dy;
+                    syB[(mu * 3 + 1) * K + c][lane] = dtg[0][mu];
+                    syB[(mu * 3 + 2) * K + c][lane] = dn[0][mu];
                     ytop[mu][0] = val[1][mu];
-                    ytop[mu][1] = dtg[1][mu] * inv_dx;
-                    ytop[mu][2] = dn[1][mu] * inv_dy;
+                    ytop[mu][1] = dtg[1][mu];
+                    ytop[mu][2] = dn[1][mu];
                 }
             }
             sHc[0][c][lane] = vhx;
@@ -337,7 +345,7 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
                     T fr = 0, fl = 0, g = 0;
 #pragma unroll
                     for (int mu = 0; mu < Q; ++mu) {
-                        const T w = (T)Gauss<Q>::w(mu);
+                        const T w = (T)(0.5 * Gauss<Q>::w(mu));   // fluxes are stored doubled
                         fr += w * sFX[mu][sk * K + c][lane];
                         fl += w * sFX[mu][sk * K + c][lane > 0 ? lane - 1 : 0];
                         g += w * sFY[mu][sk * K + c][lane];
@@ -347,8 +355,9 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
                 }
                 if (r > j0) {
                     const TA Lu = -(xd_prev[0] * inv_dx_a + (gy[0] - gy_prev[0]) * inv_dy_a);
-                    const T Lv = -((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
-                    const T Lw = -(ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
+                    // v- and w-fluxes carry the derivatives in local units
+                    const T Lv = -inv_dx * ((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
+                    const T Lw = -inv_dy * (ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
                     if (emit) {
                         const TA ucur = (TA)um;   // u-bar of row r-1 in the input set
                         if (mode == MODE_RHS) {
@@ -402,9 +411,18 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
         }
         __syncthreads();  // LDS reuse by the next tile
         if (fuse_alpha) {
-            if (jend - 2 >= j0) gather_speeds(jend - 2);
-            gather_speeds(jend - 1);
-            if (c == 0) publish_next_speeds(a.probs[tile.prob], smx[lane], smy[lane], sbad[lane]);
+            // the last two rows by one wave: no barrier between them
+            const int pw = gather_wave(jend - 1);
+            if (jend - 2 >= j0) gather_speeds(jend - 2, pw);
+            gather_speeds(jend - 1, pw);
+            if (c == pw) {
+                const double mxl = smx[lane], myl = smy[lane];
+                const long long badl = sbad[lane];
+                smx[lane] = 0.0;
+                smy[lane] = 0.0;
+                sbad[lane] = LLONG_MAX;
+                publish_next_speeds(a.probs[tile.prob], mxl, myl, badl);
+            }
         }
     }
 }
