@@ -44,8 +44,13 @@ struct hweno_handle {
     double* d_stage = nullptr;      // staging for set/get_state and rhs (double)
     size_t stage_elems = 0;
     std::vector<char> state_set;
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_def = nullptr;
+    // Step graphs: the full step, and the step without the reduction of
+    // stale wave speeds.  Speeds go stale only through set_state; after one
+    // full step every problem that can still advance has the speeds of its
+    // state (gathered by stage 3), so later steps use the lighter graph.
+    hipGraphExec_t graph = nullptr, graph_fast = nullptr;
+    hipGraph_t graph_def = nullptr, graph_fast_def = nullptr;
+    int speeds_fresh = 0;
     hweno_tuning tun{};
     Scheme sch{};
     std::string err;
@@ -243,8 +248,10 @@ static int build_tiles(hweno_handle* h) {
 static void drop_graph(hweno_handle* h) {
     if (h->graph) hipGraphExecDestroy(h->graph);
     if (h->graph_def) hipGraphDestroy(h->graph_def);
-    h->graph = nullptr;
-    h->graph_def = nullptr;
+    if (h->graph_fast) hipGraphExecDestroy(h->graph_fast);
+    if (h->graph_fast_def) hipGraphDestroy(h->graph_fast_def);
+    h->graph = h->graph_fast = nullptr;
+    h->graph_def = h->graph_fast_def = nullptr;
 }
 
 // ----------------------------------------------------------------- create
@@ -459,6 +466,7 @@ extern "C" int hweno_set_state(hweno_handle* h, int32_t prob, const double* src,
     HIP_TRY(h, hipMemcpyAsync(h->d_probs + prob, &d, sizeof d, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     h->state_set[prob] = 1;
+    h->speeds_fresh = 0;
     return HWENO_OK;
 }
 
@@ -573,15 +581,22 @@ extern "C" int hweno_rhs(hweno_handle* h, int32_t prob, double* L_out, double* U
 // (and may bracket it with events).
 enum LaunchKind { LK_OTHER = 0, LK_ALPHA = 1, LK_STAGE = 2 };
 
-template <class Rec> static int enqueue_step_with(hweno_handle* h, int use_dt_in, Rec&& rec) {
+// One step.  fast: no problem that can advance has stale speeds, so the
+// reduction kernel is left out (and with at most 256 problems the dt kernel
+// clears the step counters itself, which leaves out the reset kernel too).
+template <class Rec>
+static int enqueue_step_with(hweno_handle* h, int use_dt_in, bool fast, Rec&& rec) {
+    const int own_ctl = fast && h->nprob <= 256;
     // speeds are gathered by stage 3 of the previous step; the reduction
     // kernel only fills them in after set_state
-    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_reset(h->d_probs, h->d_ctl, h->nprob, SEL_STALE, h->stream); }));
-    HIP_TRY(h, rec(LK_ALPHA, [&] {
-        return launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
-                            h->nchunks, h->sch, SEL_STALE, 0, h->stream);
-    }));
-    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_dt(h->d_probs, h->d_ctl, h->nprob, use_dt_in, h->stream); }));
+    if (!own_ctl)
+        HIP_TRY(h, rec(LK_OTHER, [&] { return launch_reset(h->d_probs, h->d_ctl, h->nprob, SEL_STALE, h->stream); }));
+    if (!fast)
+        HIP_TRY(h, rec(LK_ALPHA, [&] {
+            return launch_alpha(h->prec, h->flux, h->dim, h->U[0].u, h->d_probs, h->d_chunks,
+                                h->nchunks, h->sch, SEL_STALE, 0, h->stream);
+        }));
+    HIP_TRY(h, rec(LK_OTHER, [&] { return launch_dt(h->d_probs, h->d_ctl, h->nprob, use_dt_in, own_ctl, h->stream); }));
     for (int mode = MODE_S1; mode <= MODE_S3; ++mode) {
         if (mode != MODE_S1 && h->cfg.alpha_stage) {
             // speeds of this stage's input (per-stage option)
@@ -598,15 +613,20 @@ template <class Rec> static int enqueue_step_with(hweno_handle* h, int use_dt_in
     return HWENO_OK;
 }
 
-static int enqueue_step(hweno_handle* h, int use_dt_in) {
-    return enqueue_step_with(h, use_dt_in, [](int, auto&& launch) { return launch(); });
+static int enqueue_step(hweno_handle* h, int use_dt_in, bool fast) {
+    int rc = enqueue_step_with(h, use_dt_in, fast, [](int, auto&& launch) { return launch(); });
+    if (rc == HWENO_OK) h->speeds_fresh = 1;
+    return rc;
 }
 
 static int launch_step(hweno_handle* h) {
-    if (!h->tun.use_graph) return enqueue_step(h, 0);
-    if (!h->graph) {
+    const bool fast = h->speeds_fresh != 0;
+    if (!h->tun.use_graph) return enqueue_step(h, 0, fast);
+    hipGraphExec_t& exec = fast ? h->graph_fast : h->graph;
+    hipGraph_t& def = fast ? h->graph_fast_def : h->graph_def;
+    if (!exec) {
         HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_step(h, 0);
+        int rc = enqueue_step_with(h, 0, fast, [](int, auto&& launch) { return launch(); });
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &g);
         if (rc) {
@@ -615,10 +635,11 @@ static int launch_step(hweno_handle* h) {
         }
         if (e != hipSuccess)
             return fail(h, HWENO_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-        h->graph_def = g;
-        HIP_TRY(h, hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0));
+        def = g;
+        HIP_TRY(h, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
     }
-    HIP_TRY(h, hipGraphLaunch(h->graph, h->stream));
+    HIP_TRY(h, hipGraphLaunch(exec, h->stream));
+    h->speeds_fresh = 1;
     return HWENO_OK;
 }
 
@@ -640,7 +661,7 @@ extern "C" int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out) 
         HIP_TRY(h, hipMemcpyAsync(h->d_probs, v.data(), sizeof(ProbDev) * h->nprob,
                                   hipMemcpyHostToDevice, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
-        rc = enqueue_step(h, 1);
+        rc = enqueue_step(h, 1, h->speeds_fresh != 0);
     } else {
         rc = launch_step(h);
     }
@@ -710,6 +731,7 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     if (rc) return rc;
     StepCtl saved_ctl{};
     HIP_TRY(h, hipMemcpy(&saved_ctl, h->d_ctl, sizeof saved_ctl, hipMemcpyDeviceToHost));
+    const int saved_fresh = h->speeds_fresh;
     const size_t ub = (size_t)((char*)h->U[0].d - (char*)h->U[0].u);
     const size_t db = (size_t)((char*)h->U[1].u - (char*)h->U[0].d);
     void* save = nullptr;
@@ -721,6 +743,7 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
         HIP_TRY(h, hipMemcpyAsync(h->d_ctl, &saved_ctl, sizeof saved_ctl, hipMemcpyHostToDevice,
                                   h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
+        h->speeds_fresh = saved_fresh;   // the restored table may hold stale speeds
         return HWENO_OK;
     };
     HIP_TRY(h, hipMemcpyAsync(save, h->U[0].u, ub + db, hipMemcpyDeviceToDevice, h->stream));
@@ -796,7 +819,8 @@ extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* 
     if (!start) return fail(h, HWENO_ERR_HIP, "event creation failed");
     HIP_TRY(h, hipEventRecord(start, h->stream));
     for (int s = 0; s < nsteps && rc == HWENO_OK; ++s) {
-        rc = enqueue_step_with(h, 0, [&](int kind, auto&& launch) -> hipError_t {
+        const bool fast = h->speeds_fresh != 0;
+        rc = enqueue_step_with(h, 0, fast, [&](int kind, auto&& launch) -> hipError_t {
             hipEvent_t a = fresh(), b = fresh();
             if (!a || !b) return hipErrorOutOfMemory;
             hipError_t e = hipEventRecord(a, h->stream);
@@ -806,6 +830,7 @@ extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* 
             kinds.push_back(kind);
             return hipEventRecord(b, h->stream);
         });
+        if (rc == HWENO_OK) h->speeds_fresh = 1;
     }
     hipEvent_t stop = rc == HWENO_OK ? fresh() : nullptr;
     if (stop) {

@@ -99,19 +99,17 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
 }
 
 // dt = min(CFL rule, t_end - t); the CFL rule is cfl*dx^e/alpha_x in 1D and
-// cfl/(alpha_x/dx^e + alpha_y/dy^e) in 2D (or the caller's step).
-__global__ void dt_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nprob) return;
-    ProbDev& P_ = probs[p];
+// cfl/(alpha_x/dx^e + alpha_y/dy^e) in 2D (or the caller's step).  Returns
+// whether the problem takes this step.
+__device__ __forceinline__ int select_dt(ProbDev& P_, const StepCtl* ctl, int use_dt_in) {
     P_.active = 0;
     P_.last = 0;
     P_.dt = 0.0;
-    if (!(P_.t < P_.t_end) || P_.err) return;
+    if (!(P_.t < P_.t_end) || P_.err) return 0;
     double dtc;
     if (use_dt_in) {
         dtc = P_.dt_in;
-        if (!(dtc > 0.0)) return;
+        if (!(dtc > 0.0)) return 0;
     } else {
         const double ax = as_double(P_.ax_bits), ay = as_double(P_.ay_bits);
         dtc = ctl->dim == 1 ? ctl->cfl * P_.dxe / ax : ctl->cfl / (ax / P_.dxe + ay / P_.dye);
@@ -121,7 +119,24 @@ __global__ void dt_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in
     P_.dt = last ? rem : dtc;
     P_.last = last;
     P_.active = 1;
-    atomicOr(&ctl->step_active, 1);
+    return 1;
+}
+
+// own_ctl: the launch is one block that holds every problem and sets the
+// step counters itself (no reset kernel before it); otherwise a reset kernel
+// has cleared them and the blocks only raise step_active.
+__global__ void dt_kernel(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, int own_ctl) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int act = p < nprob ? select_dt(probs[p], ctl, use_dt_in) : 0;
+    if (own_ctl) {
+        const int any = __syncthreads_or(act);
+        if (threadIdx.x == 0) {
+            ctl->nactive = 0;
+            ctl->step_active = any;
+        }
+    } else if (act) {
+        atomicOr(&ctl->step_active, 1);
+    }
 }
 
 // t += dt (exactly t_end on the clipped last step); counts problems still
@@ -197,8 +212,10 @@ hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* pro
     return alpha_dispatch<P_F64>(flux, dim, u, probs, chunks, nchunks, sch, sel, grid, s);
 }
 
-hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, hipStream_t s) {
-    dt_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, use_dt_in);
+hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, int own_ctl,
+                     hipStream_t s) {
+    if (own_ctl && nprob > 256) return hipErrorInvalidValue;
+    dt_kernel<<<(nprob + 255) / 256, 256, 0, s>>>(probs, ctl, nprob, use_dt_in, own_ctl);
     return hipGetLastError();
 }
 

@@ -126,7 +126,8 @@ hipError_t launch_reset(ProbDev* probs, StepCtl* ctl, int nprob, int sel, hipStr
 hipError_t launch_alpha(int prec, int flux, int dim, const void* u, ProbDev* probs,
                         const Chunk* chunks, int nchunks, const Scheme& sch, int sel,
                         int grid, hipStream_t s);
-hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, hipStream_t s);
+hipError_t launch_dt(ProbDev* probs, StepCtl* ctl, int nprob, int use_dt_in, int own_ctl,
+                     hipStream_t s);
 hipError_t launch_finish(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s);
 // Converts one problem's state between the boundary layout (double,
 // ext[((var*K + c)*ny + j)*nx + i]) and the internal planes of buf.
