@@ -290,8 +290,11 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
         load_row(j0 - 1, u0, v0, w0);
         load_row(j0, up, vp, wp);
         T ytop[Q][3];            // top-face values of the previous row (this lane, comp)
-        TA xd_prev[3] = {0, 0, 0};
-        TA gy_prev[3] = {0, 0, 0};
+        // previous row's flux sums: x differences and y sums of the
+        // cell-average fluxes in the accumulation type, of the derivative
+        // fluxes in T
+        TA xdu_prev = 0, gyu_prev = 0;
+        T xdd_prev[2] = {0, 0}, gyd_prev[2] = {0, 0};
         T hat_prev[2] = {0, 0};
 
         for (int r = j0 - 1; r <= jend; ++r) {
@@ -411,7 +414,10 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                 }
                 __syncthreads();  // B: fluxes ready
                 // ---- S: residual and RK stage of row r-1 ------------------
-                TA xd[3], gy[3];
+                // The derivative fluxes are differenced in T: the difference of
+                // two T values rounded to T is what a wider difference rounds to.
+                TA xdu = 0, gyu = 0;
+                T xdd[2], gyd[2];
 #pragma unroll
                 for (int sk = 0; sk < 3; ++sk) {
                     T fr = 0, fl = 0, g = 0;
@@ -422,14 +428,19 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                         fl += w * sFX[mu][sk * K + c][lane > 0 ? lane - 1 : 0];
                         g += w * sFY[mu][sk * K + c][lane];
                     }
-                    xd[sk] = (TA)fr - (TA)fl;
-                    gy[sk] = (TA)g;
+                    if (sk == 0) {
+                        xdu = (TA)fr - (TA)fl;
+                        gyu = (TA)g;
+                    } else {
+                        xdd[sk - 1] = fr - fl;
+                        gyd[sk - 1] = g;
+                    }
                 }
                 if (r > j0) {
-                    const TA Lu = -(xd_prev[0] * inv_dx_a + (gy[0] - gy_prev[0]) * inv_dy_a);
+                    const TA Lu = -(xdu_prev * inv_dx_a + (gyu - gyu_prev) * inv_dy_a);
                     // v- and w-fluxes carry the derivatives in local units
-                    const T Lv = -inv_dx * ((T)xd_prev[1] + rx * (T)(gy[1] - gy_prev[1]));
-                    const T Lw = -inv_dy * (ry * (T)xd_prev[2] + (T)(gy[2] - gy_prev[2]));
+                    const T Lv = -inv_dx * (xdd_prev[0] + rx * (gyd[0] - gyd_prev[0]));
+                    const T Lw = -inv_dy * (ry * xdd_prev[1] + (gyd[1] - gyd_prev[1]));
                     if (emit) {
                         const TA ucur = (TA)um;   // u-bar of row r-1 in the input set
                         if (mode == MODE_RHS) {
@@ -466,10 +477,12 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
                         }
                     }
                 }
+                xdu_prev = xdu;
+                gyu_prev = gyu;
 #pragma unroll
-                for (int sk = 0; sk < 3; ++sk) {
-                    xd_prev[sk] = xd[sk];
-                    gy_prev[sk] = gy[sk];
+                for (int sk = 0; sk < 2; ++sk) {
+                    xdd_prev[sk] = xdd[sk];
+                    gyd_prev[sk] = gyd[sk];
                 }
             }
             hat_prev[0] = vhat;
