@@ -70,6 +70,15 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
                 }
             }
         }
+        // thread 0 publishes the chunk's maxima; it reads the slots before
+        // the reduction (lower bounds of their final values; see publish_max;
+        // read at the start, when every block starts at once, they are mostly
+        // still zero)
+        uint64_t seen_x = 0, seen_y = 0;
+        if (threadIdx.x == 0) {
+            seen_x = peek_slot(&P_.ax_bits);
+            seen_y = peek_slot(&P_.ay_bits);
+        }
         mx = wave_max_d(mx);
         my = wave_max_d(my);
         if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
@@ -87,8 +96,8 @@ __global__ void __launch_bounds__(256) alpha_kernel(const void* uptr, ProbDev* p
                 bad = sbad[w] < bad ? sbad[w] : bad;
             }
             // non-negative doubles order like their bit patterns
-            atomicMax((unsigned long long*)&P_.ax_bits, (unsigned long long)__double_as_longlong(mx));
-            atomicMax((unsigned long long*)&P_.ay_bits, (unsigned long long)__double_as_longlong(my));
+            publish_max(&P_.ax_bits, mx, seen_x);
+            publish_max(&P_.ay_bits, my, seen_y);
             if (bad != LLONG_MAX) {
                 atomicMin((long long*)&P_.bad_cell, bad);
                 atomicOr(&P_.err, sel == SEL_ACTIVE ? ERR_STAGE_BAD : ERR_STATE_BAD);

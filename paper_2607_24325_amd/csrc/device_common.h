@@ -190,14 +190,16 @@ template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
 // bits as a plain evaluation of the definition (time steps then agree
 // exactly with a reference run, also along trajectories that end in a
 // non-admissible state); returns false if U is not finite or (Euler)
-// rho <= 0 or p <= 0.
+// rho <= 0 or p <= 0 (sx, sy are then meaningless).  Straight-line code: the
+// sound speed is evaluated whatever the admissibility test says and selected
+// afterwards, so that a caller can schedule the chain with other work.
 template <int FLUX, int DIM, int K>
 __device__ __forceinline__ bool wave_speed(const double* u, const Scheme& sch, double& sx,
                                            double& sy) {
 #pragma clang fp contract(off)
     bool ok = true;
 #pragma unroll
-    for (int c = 0; c < K; ++c) ok = ok && isfinite(u[c]);
+    for (int c = 0; c < K; ++c) ok = ok & (bool)isfinite(u[c]);
     if (FLUX == F_ADV) {
         sx = fabs(sch.adv[0]);
         sy = fabs(sch.adv[1]);
@@ -210,8 +212,9 @@ __device__ __forceinline__ bool wave_speed(const double* u, const Scheme& sch, d
         const double vy = DIM == 2 ? u[2] / rho : 0.0;
         const double ke = 0.5 * rho * (vx * vx + vy * vy);
         const double pr = (g - 1.0) * (u[K - 1] - ke);
-        ok = ok && rho > 0.0 && pr > 0.0;
-        const double cs = ok ? sqrt(g * pr / rho) : 0.0;
+        ok = ok & (rho > 0.0) & (pr > 0.0);
+        const double cs2 = g * pr / rho;
+        const double cs = sqrt(ok ? cs2 : 1.0);
         sx = fabs(vx) + cs;
         sy = fabs(vy) + cs;
     }
@@ -233,14 +236,30 @@ __device__ __forceinline__ long long wave_min_ll(long long v) {
     return v;
 }
 
+// Speeds only grow during a launch and their slots start at zero, so any
+// relaxed read of a slot during the launch is a lower bound of its final
+// value: a block maximum that does not exceed it has nothing to add, and most
+// blocks skip the atomic (every block of a problem targets the same address,
+// where atomics serialize).  Callers read the slot (peek_slot) some time
+// before they publish, so that the read's latency overlaps their work.
+__device__ __forceinline__ uint64_t peek_slot(const uint64_t* slot) {
+    return __hip_atomic_load(const_cast<uint64_t*>(slot), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void publish_max(uint64_t* slot, double v, uint64_t seen) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    if (b > seen) atomicMax((unsigned long long*)slot, b);
+}
+
 // Folds reduced speeds and a first bad cell into the problem's slots for the
-// state being written (one lane calls this).  Speeds are non-negative, so
-// their bit patterns order as unsigned integers.
-__device__ __forceinline__ void publish_reduced(ProbDev& P, double mx, double my,
-                                                long long bad) {
-    atomicMax((unsigned long long*)&P.ax_next, (unsigned long long)__double_as_longlong(mx));
-    if (my > 0.0)
-        atomicMax((unsigned long long*)&P.ay_next, (unsigned long long)__double_as_longlong(my));
+// state being written (one lane calls this; seen_x, seen_y: earlier reads of
+// the two slots).  Speeds are non-negative, so their bit patterns order as
+// unsigned integers.
+__device__ __forceinline__ void publish_reduced(ProbDev& P, double mx, double my, long long bad,
+                                                uint64_t seen_x, uint64_t seen_y) {
+    publish_max(&P.ax_next, mx, seen_x);
+    if (my > 0.0) publish_max(&P.ay_next, my, seen_y);
     if (bad != LLONG_MAX) {
         atomicMin((long long*)&P.bad_cell, bad);
         atomicOr(&P.err, ERR_STATE_BAD);
@@ -250,11 +269,12 @@ __device__ __forceinline__ void publish_reduced(ProbDev& P, double mx, double my
 // Wave-level version: every lane brings its values, lane 0 publishes.  The
 // bad-cell minimum is only formed when some lane has one.
 __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, double my,
-                                                    long long bad) {
+                                                    long long bad, uint64_t seen_x,
+                                                    uint64_t seen_y) {
     mx = wave_max_d(mx);
     my = wave_max_d(my);
     if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
-    if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad);
+    if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad, seen_x, seen_y);
 }
 
 // --------------------------------------- classical smoothness indicator ---

@@ -54,6 +54,10 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
         // problem-table fields are copied before any store: read after one,
         // they would be reloaded (possible aliasing) and waited for
         const int64_t off_u = P_.off_u, off_d = P_.off_d;
+        // stage 3: thread 0, which publishes the tile's speed maximum, reads
+        // the slot now (a lower bound of its final value; see publish_max)
+        uint64_t seen_x = 0;
+        if (mode == MODE_S3 && tid == 0) seen_x = peek_slot(&a.probs[tile.prob].ax_next);
 
         for (int k = tid; k < NL; k += 256) {
             const int src = bc_map(c0 - 2 + k, nx, bcx);
@@ -248,7 +252,7 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
                 mx = fmax(mx, s_mx[w]);
                 bad = s_bad[w] < bad ? s_bad[w] : bad;
             }
-            publish_reduced(a.probs[tile.prob], mx, 0.0, bad);
+            publish_reduced(a.probs[tile.prob], mx, 0.0, bad, seen_x, 0);
         }
     }
 }

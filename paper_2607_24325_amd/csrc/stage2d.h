@@ -493,16 +493,17 @@ __global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(S
             wm = w0; w0 = wp; wp = wn_;
         }
         __syncthreads();  // LDS reuse by the next tile
-        if (fuse_alpha) {
+        if (fuse_alpha && c == gather_wave(jend - 1)) {
+            // the slots are read first: the last row's gather covers the read
+            ProbDev& Pw = a.probs[tile.prob];
+            const uint64_t seen_x = peek_slot(&Pw.ax_next), seen_y = peek_slot(&Pw.ay_next);
             gather_speeds(jend - 1);
-            if (c == gather_wave(jend - 1)) {
-                const double mxl = smx[lane], myl = smy[lane];
-                const long long badl = sbad[lane];
-                smx[lane] = 0.0;
-                smy[lane] = 0.0;
-                sbad[lane] = LLONG_MAX;
-                publish_next_speeds(a.probs[tile.prob], mxl, myl, badl);
-            }
+            const double mxl = smx[lane], myl = smy[lane];
+            const long long badl = sbad[lane];
+            smx[lane] = 0.0;
+            smy[lane] = 0.0;
+            sbad[lane] = LLONG_MAX;
+            publish_next_speeds(Pw, mxl, myl, badl, seen_x, seen_y);
         }
     }
 }

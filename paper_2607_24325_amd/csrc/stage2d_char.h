@@ -429,12 +429,14 @@ __global__ void __launch_bounds__(256, (P == P_F64 ? 1 : 2)) stage2d_char_kernel
             if (jend - 2 >= j0) gather_speeds(jend - 2, pw);
             gather_speeds(jend - 1, pw);
             if (c == pw) {
+                ProbDev& Pw = a.probs[tile.prob];
+                const uint64_t seen_x = peek_slot(&Pw.ax_next), seen_y = peek_slot(&Pw.ay_next);
                 const double mxl = smx[lane], myl = smy[lane];
                 const long long badl = sbad[lane];
                 smx[lane] = 0.0;
                 smy[lane] = 0.0;
                 sbad[lane] = LLONG_MAX;
-                publish_next_speeds(a.probs[tile.prob], mxl, myl, badl);
+                publish_next_speeds(Pw, mxl, myl, badl, seen_x, seen_y);
             }
         }
     }
