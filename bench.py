@@ -29,15 +29,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 VEC_TFLOPS = 78.6              # MI355X vector FP64, = non-packed FP32 (FMA counted as 2)
-# FP operations per cell-stage of the 2D Euler stage (Q = 2), from the FP
-# instruction counters of the stage kernel restricted to output-producing
-# lanes and rows (profiles/stage2d_euler2048.md)
-ALU_FLOP_PER_CELL_STAGE = 2764.0
+# FP operations per cell-stage of the 2D Euler stage (Q = 2): the FP
+# instruction counters of the stage kernel (FMA = 2, other FP instructions 1)
+# restricted to output-producing lanes and rows (profiles/stage2d_euler2048.md)
+ALU_FLOP_PER_CELL_STAGE = 2658.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) for the kernel sources of this hash; any change of
 # the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "13d107530e2675a3"
-PROFILED_TRAFFIC = {"f32acc64": 832.0e6, "f64": 1246.0e6}
+PROFILED_SOURCES = "ec55f61ced12db89"
+PROFILED_TRAFFIC = {"f32acc64": 821.3e6, "f64": 1244.0e6}
 
 
 def kernel_sources_hash() -> str:
