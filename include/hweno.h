@@ -172,7 +172,10 @@ int hweno_alpha(hweno_handle* h, int32_t prob, double* ax, double* ay);
  * array of nprob time steps (a problem's step is still clipped onto t_end;
  * a value <= 0 skips the problem).  dt_out: NULL, or a host array of nprob
  * doubles receiving the steps taken (then the call synchronises).
- * Otherwise the call only enqueues. Errors: ERR_STATE before set_state. */
+ * Otherwise the call only enqueues. Errors: ERR_STATE before set_state.
+ * The speeds of a state are reduced from its cell averages by the first
+ * step after set_state; later steps use the speeds stage 3 gathered from
+ * the state it wrote (the same bits as a fresh reduction). */
 int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out);
 
 /* Advances every problem to its t_end with the CFL rule.  Synchronising.
@@ -205,7 +208,8 @@ int hweno_autotune(hweno_handle* h, hweno_tuning* best);
 /* Per-kernel timing of nsteps steps (CFL rule), launched eagerly on the
  * handle's stream with a HIP event pair around every kernel.  Synchronising.
  * total_ms: first to last event; stage_ms: sum of the fused stage kernels;
- * alpha_ms: wave-speed reductions; other_ms: dt and time-update kernels. */
+ * alpha_ms: wave-speed reductions (none once stage 3 has gathered the
+ * speeds); other_ms: dt and time-update kernels. */
 typedef struct {
     double total_ms;
     double stage_ms;
