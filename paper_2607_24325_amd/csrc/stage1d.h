@@ -15,8 +15,19 @@
 
 namespace hweno {
 
+// Workgroups per CU the register allocation must allow.  With FP32 faces
+// the staging in LDS (21.6 KB per workgroup) admits seven; stage 3 carries
+// the FP64 wave-speed reduction and the characteristic projections need more
+// registers.  With FP64 faces LDS (37 KB) admits four and the allocation is
+// left to the compiler.
+template <int P, int mode, bool CH> constexpr int stage1d_min_blocks() {
+    return P == P_F64 ? 1
+                      : CH ? (mode == MODE_S3 ? 4 : 5)
+                           : (mode == MODE_S3 || mode == MODE_RHS ? 5 : 6);
+}
+
 template <int P, int K, int FLUX, int mode, bool CH>
-__global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
+__global__ void __launch_bounds__(256, (stage1d_min_blocks<P, mode, CH>())) stage1d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
@@ -26,7 +37,9 @@ __global__ void __launch_bounds__(256) stage1d_kernel(StageArgs a) {
     __shared__ TD sv[K][NL];
     __shared__ T sR[2 * K][256];         // (u, u_x) at x_{i+1/2} from cell i
     __shared__ T sL[2 * K][256];         // (u, u_x) at x_{i-1/2} from cell i
-    __shared__ T sF[2 * K][256];         // (f-hat, h-hat) at the right interface of cell t
+    // (f-hat, h-hat) at the right interface of cell t: written over sR, whose
+    // entry t only thread t reads (right before it writes the flux there)
+    T (&sF)[2 * K][256] = sR;
     __shared__ double s_mx[4];           // stage 3: per-wave maxima of the wave speeds
     __shared__ long long s_bad[4];
 
