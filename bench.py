@@ -262,7 +262,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded quadrant states + isentropic vortex)",
         "config": {"workload": f"2D Euler {n}x{n} periodic, Q=2, CFL 0.5, quadrant+vortex seed 7",
-                   "precision": "F32 bulk, FP64 cell averages and flux differences",
+                   "precision": "F32 bulk, FP64 cell averages and cell-average flux differences",
                    "cells": ncell, "unknowns_per_cell": 12},
         "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": VEC_TFLOPS, "unit": "TFLOP/s",
                      "frac": alu_tflops / VEC_TFLOPS, "traffic": traffic,
