@@ -59,18 +59,17 @@ def algorithmic_bytes_per_cell_stage(K: int, D: int, su: int, sd: int) -> float:
 
 def timed_run(h, stream, steps: int, warmup: int, allow_nonfinite: bool = False):
     """Warm-up steps, then `steps` HIP-graph steps bracketed by events on the
-    handle's stream (the step time), then `steps` eagerly launched steps with
-    an event pair around every kernel (the per-kernel times)."""
+    handle's stream (the step time; the library replays runs of 8 steps as
+    one graph, built during the warm-up), then `steps` eagerly launched steps
+    with an event pair around every kernel (the per-kernel times)."""
     import torch
-    for _ in range(warmup):
-        h.step()
+    h.steps(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     tw0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
-        h.step()
+    h.steps(steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw0

@@ -178,6 +178,13 @@ int hweno_alpha(hweno_handle* h, int32_t prob, double* ax, double* ay);
  * the state it wrote (the same bits as a fresh reduction). */
 int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out);
 
+/* nsteps steps (Sec. 2.1 Step 4, Sec. 2.2 Step 4) with the CFL rule, each
+ * as hweno_step(h, NULL, NULL) would take it (problems at their t_end do not
+ * move).  Only enqueues.  In graph mode, runs of 8 steps are replayed as one
+ * graph, which spares the launch gaps between graphs.  Errors: ERR_ARG for
+ * nsteps < 0, ERR_STATE before set_state. */
+int hweno_steps(hweno_handle* h, int32_t nsteps);
+
 /* Advances every problem to its t_end with the CFL rule.  Synchronising.
  * steps_out (may be NULL) receives the number of steps of the longest run.
  * Errors: ERR_NONFINITE (names the problem and cell), ERR_STATE. */

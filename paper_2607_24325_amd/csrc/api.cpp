@@ -51,6 +51,11 @@ struct hweno_handle {
     hipGraphExec_t graph = nullptr, graph_fast = nullptr;
     hipGraph_t graph_def = nullptr, graph_fast_def = nullptr;
     int speeds_fresh = 0;
+    // STEPS_PER_GRAPH lighter steps in one graph (hweno_steps, run_to_time):
+    // kernels inside a graph follow each other without a gap, while separate
+    // graph launches on a stream are several microseconds apart
+    hipGraphExec_t graph_multi = nullptr;
+    hipGraph_t graph_multi_def = nullptr;
     hweno_tuning tun{};
     Scheme sch{};
     std::string err;
@@ -250,8 +255,10 @@ static void drop_graph(hweno_handle* h) {
     if (h->graph_def) hipGraphDestroy(h->graph_def);
     if (h->graph_fast) hipGraphExecDestroy(h->graph_fast);
     if (h->graph_fast_def) hipGraphDestroy(h->graph_fast_def);
-    h->graph = h->graph_fast = nullptr;
-    h->graph_def = h->graph_fast_def = nullptr;
+    if (h->graph_multi) hipGraphExecDestroy(h->graph_multi);
+    if (h->graph_multi_def) hipGraphDestroy(h->graph_multi_def);
+    h->graph = h->graph_fast = h->graph_multi = nullptr;
+    h->graph_def = h->graph_fast_def = h->graph_multi_def = nullptr;
 }
 
 // ----------------------------------------------------------------- create
@@ -643,6 +650,52 @@ static int launch_step(hweno_handle* h) {
     return HWENO_OK;
 }
 
+constexpr int STEPS_PER_GRAPH = 8;
+
+// Captures STEPS_PER_GRAPH lighter steps as one graph (speeds must be current).
+static int capture_multi(hweno_handle* h) {
+    HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = HWENO_OK;
+    for (int k = 0; k < STEPS_PER_GRAPH && rc == HWENO_OK; ++k)
+        rc = enqueue_step_with(h, 0, true, [](int, auto&& launch) { return launch(); });
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(h, HWENO_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    h->graph_multi_def = g;
+    HIP_TRY(h, hipGraphInstantiate(&h->graph_multi, g, nullptr, nullptr, 0));
+    return HWENO_OK;
+}
+
+// n steps with the CFL rule, enqueued: the first step after set_state alone,
+// then whole graphs of STEPS_PER_GRAPH steps, then single steps.  In graph
+// mode the multi-step graph is built as soon as the speeds are current, also
+// when n does not reach it, so that a warm-up call leaves nothing to build.
+static int launch_steps(hweno_handle* h, int64_t n) {
+    int64_t done = 0;
+    int rc = HWENO_OK;
+    if (!h->tun.use_graph) {
+        for (; done < n && rc == HWENO_OK; ++done) rc = launch_step(h);
+        return rc;
+    }
+    if (n > 0 && !h->speeds_fresh) {
+        rc = launch_step(h);
+        if (rc) return rc;
+        ++done;
+    }
+    if (h->speeds_fresh && !h->graph_multi) {
+        rc = capture_multi(h);
+        if (rc) return rc;
+    }
+    for (; n - done >= STEPS_PER_GRAPH; done += STEPS_PER_GRAPH)
+        HIP_TRY(h, hipGraphLaunch(h->graph_multi, h->stream));
+    for (; done < n && rc == HWENO_OK; ++done) rc = launch_step(h);
+    return rc;
+}
+
 static int all_set(hweno_handle* h) {
     for (int p = 0; p < h->nprob; ++p)
         if (!h->state_set[p]) return fail(h, HWENO_ERR_STATE, "problem %d has no state yet", p);
@@ -676,6 +729,14 @@ extern "C" int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out) 
     return HWENO_OK;
 }
 
+extern "C" int hweno_steps(hweno_handle* h, int32_t nsteps) {
+    if (!h) return HWENO_ERR_ARG;
+    if (nsteps < 0) return fail(h, HWENO_ERR_ARG, "nsteps must be >= 0");
+    int rc = all_set(h);
+    if (rc) return rc;
+    return launch_steps(h, nsteps);
+}
+
 extern "C" int hweno_run_to_time(hweno_handle* h, int64_t* steps_out) {
     if (!h) return HWENO_ERR_ARG;
     int rc = all_set(h);
@@ -686,10 +747,8 @@ extern "C" int hweno_run_to_time(hweno_handle* h, int64_t* steps_out) {
     const int64_t steps0 = ctl.steps;
     int batch = 4;
     for (;;) {
-        for (int k = 0; k < batch; ++k) {
-            rc = launch_step(h);
-            if (rc) return rc;
-        }
+        rc = launch_steps(h, batch);
+        if (rc) return rc;
         HIP_TRY(h, hipMemcpyAsync(&ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         if (ctl.nactive == 0) break;

@@ -58,7 +58,7 @@ class HwenoError(RuntimeError):
 
 _lib = None
 EXPORTS = ["hweno_default_config", "hweno_workspace_bytes", "hweno_create", "hweno_set_state",
-           "hweno_get_state", "hweno_rhs", "hweno_alpha", "hweno_step", "hweno_run_to_time",
+           "hweno_get_state", "hweno_rhs", "hweno_alpha", "hweno_step", "hweno_steps", "hweno_run_to_time",
            "hweno_sync", "hweno_get_tuning", "hweno_set_tuning", "hweno_autotune",
            "hweno_timed_steps", "hweno_destroy", "hweno_last_error"]
 
@@ -83,6 +83,7 @@ def lib():
         L.hweno_rhs.argtypes = [H, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]
         L.hweno_alpha.argtypes = [H, C.c_int32, P(C.c_double), P(C.c_double)]
         L.hweno_step.argtypes = [H, C.c_void_p, C.c_void_p]
+        L.hweno_steps.argtypes = [H, C.c_int32]
         L.hweno_run_to_time.argtypes = [H, P(C.c_int64)]
         L.hweno_sync.argtypes = [H]
         L.hweno_get_tuning.argtypes = [H, P(hweno_tuning)]
@@ -214,6 +215,10 @@ class Handle:
         self._check(lib().hweno_step(self.h, None if dtin is None else dtin.ctypes.data,
                                      None if dtout is None else dtout.ctypes.data))
         return dtout
+
+    def steps(self, n: int):
+        """n steps with the CFL rule (enqueued; runs of 8 as one graph)."""
+        self._check(lib().hweno_steps(self.h, int(n)))
 
     def run_to_time(self) -> int:
         steps = C.c_int64()

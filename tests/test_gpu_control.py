@@ -111,3 +111,33 @@ def test_light_step_counts_and_final_time():
         assert t == spec.t_end
         assert scaled_err(g, ref, natural_scales(spec, st)) < 1e-10
     assert n == max(counts)
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_steps_equal_single_steps(graph):
+    """hweno_steps (runs of 8 steps replayed as one graph) takes the same
+    steps as hweno_step called one at a time: the same bits, the same times,
+    and a problem that reaches its t_end on the way stays there."""
+    cfg = _cfg()
+    spec0, s0 = W.quadrant_vortex_2d(64, seed=31)
+    spec1, s1 = W.quadrant_vortex_2d(40, seed=32, t_end=0.01)
+    finals = []
+    for batched in (True, False):
+        with hw.Handle([spec0, spec1], cfg) as h:
+            h.set_tuning(use_graph=graph)
+            h.set_state(0, s0)
+            h.set_state(1, s1)
+            if batched:
+                h.steps(5)
+                h.steps(14)
+            else:
+                for _ in range(19):
+                    h.step()
+            finals.append([h.get_state(k) for k in range(2)])
+    for k in range(2):
+        (a, ta), (b, tb) = finals[0][k], finals[1][k]
+        assert ta == tb and np.array_equal(a, b), k
+    assert finals[0][1][1] == spec1.t_end
+    ref, n = O.run(oproblem(spec1, cfg), s1, 0.0, spec1.t_end, CFL)
+    assert n < 19
+    assert scaled_err(finals[0][1][0], ref, natural_scales(spec1, s1)) < 1e-10
