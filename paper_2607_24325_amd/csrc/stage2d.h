@@ -179,8 +179,14 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
     }
 }
 
+// Workgroups per CU, as the LDS of the face and flux arrays allows them (they
+// grow with Q and with the width of T); the register allocation follows.
+template <int P, int Q> constexpr int stage2d_min_blocks() {
+    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : 3);
+}
+
 template <int P, int K, int Q, int FLUX, int mode>
-__global__ void __launch_bounds__(64 * K, (P == P_F64 ? 2 : 3)) stage2d_kernel(StageArgs a) {
+__global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
