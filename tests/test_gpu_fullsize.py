@@ -113,3 +113,23 @@ def test_fullsize_characteristic_step_sampled(workload, prec, floor):
         err = scaled_err_planes(got, ref, S)
         bar = np.maximum(floor, 10.0 * sens)
         assert np.all(err <= bar), (i0, j0, err.max(), bar.min())
+
+
+def test_fullsize_steps_as_benchmarked_equal_single_steps(workload):
+    """The benchmark times hweno_steps (runs of eight steps replayed as one
+    graph): at the full size, nine steps taken that way (one, then a graph
+    of eight) give the bits of nine single steps."""
+    spec, st = workload
+    cfg = hw.default_config(2, precision=hw.F32_ACC64, gauss_q=2, cfl=0.5)
+    outs = []
+    for batched in (True, False):
+        with hw.Handle([spec], cfg) as h:
+            h.set_state(0, st)
+            if batched:
+                h.steps(9)
+            else:
+                for _ in range(9):
+                    h.step()
+            outs.append(h.get_state(0))
+    (a, ta), (b, tb) = outs
+    assert ta == tb and np.array_equal(a, b)
