@@ -51,6 +51,18 @@ template <class V> __device__ __forceinline__ V neg_if(V x, bool neg) { return n
 
 __device__ __forceinline__ double as_double(uint64_t b) { return __longlong_as_double((long long)b); }
 
+// Element idx of one plane of a problem (at most 2^29 cells of at most 8
+// bytes, so byte offsets fit in 32 bits): a wave-uniform base plus a 32-bit
+// offset, which the global memory instructions take as an SGPR base and a
+// VGPR offset, so that no lane forms a 64-bit address.
+template <class X> __device__ __forceinline__ X& plane_at(X* base, uint32_t idx) {
+    return *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(X));
+}
+template <class X> __device__ __forceinline__ const X& plane_at(const X* base, uint32_t idx) {
+    return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) +
+                                       idx * (uint32_t)sizeof(X));
+}
+
 // Whole-wave lane shifts through DPP (wave_shr:1 / wave_shl:1 of the GFX9
 // data-parallel primitives): lane l receives lane l-1 (from_left) or lane l+1
 // (from_right); the lane at the end of the wave, which has no source, gets 0

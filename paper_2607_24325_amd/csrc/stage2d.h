@@ -181,12 +181,14 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
 
 // Workgroups per CU, as the LDS of the face and flux arrays allows them (they
 // grow with Q and with the width of T); the register allocation follows.
-template <int P, int Q> constexpr int stage2d_min_blocks() {
-    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : 3);
+// Stage 1, which reads no U^n and no saved hats, fits four FP32-face
+// workgroups in 128 registers; the other stages would spill there.
+template <int P, int Q, int mode> constexpr int stage2d_min_blocks() {
+    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : (mode == MODE_S1 ? 4 : 3));
 }
 
 template <int P, int K, int Q, int FLUX, int mode>
-__global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_kernel(StageArgs a) {
+__global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) stage2d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
@@ -199,7 +201,8 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_
     __shared__ long long sbad[64];        // stage 3: per-lane first non-admissible cell
 
     const int lane = threadIdx.x & 63;
-    const int c = threadIdx.x >> 6;  // component of this wave
+    // component of this wave (uniform: the plane pointers stay in SGPRs)
+    const int c = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const Scheme& sch = a.sch;
     const int squared = sch.weights == W_BETA2 || (sch.weights == W_PAPER);
     const Flux<T, FLUX, K, 0> FXf(sch);
@@ -256,7 +259,7 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_
         TD* Ov = (TD*)a.out.d + off_d + c * plane;
         TD* Ow = (TD*)a.out.d + off_d + (K + c) * plane;
 
-        auto row_ptr = [&](int j) { return (int64_t)bc_map(j, ny, bcy) * nx + li; };
+        auto row_ptr = [&](int j) { return (uint32_t)(bc_map(j, ny, bcy) * nx + li); };
         // Solid walls: in a mirror image across x the x momentum (component
         // 1) is odd and the other averages even, and v-bar has the opposite
         // parity of its quantity; across y likewise with component 2 and
@@ -264,12 +267,12 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_
         const bool mx = FLUX == F_EULER && wall_mirrored(gi, nx, bcx);
         const bool nux = mx && c == 1, nvx = mx && c != 1, nwx = mx && c == 1;
         auto load_row = [&](int j, TU& u, TD& v, TD& w) {
-            const int64_t o = row_ptr(j);
+            const uint32_t o = row_ptr(j);
             const bool my = FLUX == F_EULER && wall_mirrored(j, ny, bcy);
             const bool nuy = my && c == 2, nvy = my && c == 2, nwy = my && c != 2;
-            u = neg_if(Uu[o], nux != nuy);
-            v = neg_if(Uv[o], nvx != nvy);
-            w = neg_if(Uw[o], nwx != nwy);
+            u = neg_if(plane_at(Uu, o), nux != nuy);
+            v = neg_if(plane_at(Uv, o), nvx != nvy);
+            w = neg_if(plane_at(Uw, o), nwx != nwy);
         };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
 
@@ -309,14 +312,14 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_
             TA unr = 0;
             T hvr = 0, hwr = 0;
             const bool emit = r > j0 && out_col;   // row r-1 is an output row
-            const int64_t oo = (int64_t)(r - 1) * nx + gi;  // output row r-1 (in range if emit)
+            const uint32_t oo = (uint32_t)((r - 1) * nx + gi);  // output row r-1 (in range if emit)
             if (mode == MODE_S2 || mode == MODE_S3) {
                 // unconditional (lanes without output read element 0) so that
                 // the loads stay in flight until the epilogue uses them
-                const int64_t ol = emit ? oo : 0;
-                unr = (TA)Un[ol];
-                hvr = (T)Hv[ol];
-                hwr = (T)Hw[ol];
+                const uint32_t ol = emit ? oo : 0u;
+                unr = (TA)plane_at(Un, ol);
+                hvr = (T)plane_at(Hv, ol);
+                hwr = (T)plane_at(Hw, ol);
             }
 
             // ---- R: reconstruct cell (gi, r), component c -------------------
@@ -461,23 +464,23 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q>())) stage2d_
                             const TA dta = (TA)dt;
                             const T dtt = (T)dt;
                             if (mode == MODE_S1) {
-                                Ou[oo] = (TU)(ucur + dta * Lu);
-                                Ov[oo] = (TD)(hat_prev[0] + dtt * Lv);
-                                Ow[oo] = (TD)(hat_prev[1] + dtt * Lw);
-                                Hv[oo] = (TD)hat_prev[0];
-                                Hw[oo] = (TD)hat_prev[1];
+                                plane_at(Ou, oo) = (TU)(ucur + dta * Lu);
+                                plane_at(Ov, oo) = (TD)(hat_prev[0] + dtt * Lv);
+                                plane_at(Ow, oo) = (TD)(hat_prev[1] + dtt * Lw);
+                                plane_at(Hv, oo) = (TD)hat_prev[0];
+                                plane_at(Hw, oo) = (TD)hat_prev[1];
                             } else if (mode == MODE_S2) {
-                                Ou[oo] = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
-                                Ov[oo] = (TD)((T)0.75 * hvr + (T)0.25 * (hat_prev[0] + dtt * Lv));
-                                Ow[oo] = (TD)((T)0.75 * hwr + (T)0.25 * (hat_prev[1] + dtt * Lw));
+                                plane_at(Ou, oo) = (TU)((TA)0.75 * unr + (TA)0.25 * (ucur + dta * Lu));
+                                plane_at(Ov, oo) = (TD)((T)0.75 * hvr + (T)0.25 * (hat_prev[0] + dtt * Lv));
+                                plane_at(Ow, oo) = (TD)((T)0.75 * hwr + (T)0.25 * (hat_prev[1] + dtt * Lw));
                             } else {
                                 const TA third = (TA)(1.0 / 3.0), two3 = (TA)(2.0 / 3.0);
                                 const TU nu = (TU)(third * unr + two3 * (ucur + dta * Lu));
-                                Ou[oo] = nu;
+                                plane_at(Ou, oo) = nu;
                                 snew[c][lane] = (double)nu;
-                                Ov[oo] = (TD)((T)(1.0 / 3.0) * hvr +
+                                plane_at(Ov, oo) = (TD)((T)(1.0 / 3.0) * hvr +
                                               (T)(2.0 / 3.0) * (hat_prev[0] + dtt * Lv));
-                                Ow[oo] = (TD)((T)(1.0 / 3.0) * hwr +
+                                plane_at(Ow, oo) = (TD)((T)(1.0 / 3.0) * hwr +
                                               (T)(2.0 / 3.0) * (hat_prev[1] + dtt * Lw));
                             }
                         }
