@@ -36,8 +36,8 @@ ALU_FLOP_PER_CELL_STAGE = 2658.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) for the kernel sources of this hash; any change of
 # the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "6c2be75a7d258ba2"
-PROFILED_TRAFFIC = {"f32acc64": 821.3e6, "f64": 1244.0e6}
+PROFILED_SOURCES = "dd33cfd9ecd86079"
+PROFILED_TRAFFIC = {"f32acc64": 821.9e6, "f64": 1243.6e6}
 
 
 def kernel_sources_hash() -> str:
