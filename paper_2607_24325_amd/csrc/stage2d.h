@@ -161,30 +161,39 @@ template <class T> __device__ __forceinline__ void transpose15(const T* C, T* D)
 }
 
 // Lax-Friedrichs flux at one edge point, all components, TWICE its value:
-// out = 2 (f, f^v, f^w) = (f(L) + f(R)) - alpha (R - L).  The factor 1/2 is
-// folded into the Gauss weights of the residual, which saves one multiply per
-// output (halving and doubling are exact in binary floating point).
+// out = 2 (f, f^v, f^w) = (f(L) + alpha L) + (f(R) - alpha R).  The factor
+// 1/2 is folded into the Gauss weights of the residual, which saves one
+// multiply per output (halving and doubling are exact in binary floating
+// point); the two sides are accumulated one after the other, so that only
+// one side's values and fluxes are live at a time.
 template <class T, int FLUX, int K, int DIR>
 __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T* UL, const T* VL,
                                         const T* WL, const T* UR, const T* VR, const T* WR,
                                         T alpha, T* out) {
-    T fL[K], fvL[K], fwL[K], fR[K], fvR[K], fwR[K];
-    F.side(UL, VL, WL, fL, fvL, fwL);
-    F.side(UR, VR, WR, fR, fvR, fwR);
+    T f[K], fv[K], fw[K];
+    F.side(UL, VL, WL, f, fv, fw);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        out[c] = (fL[c] + fR[c]) - alpha * (UR[c] - UL[c]);
-        out[K + c] = (fvL[c] + fvR[c]) - alpha * (VR[c] - VL[c]);
-        out[2 * K + c] = (fwL[c] + fwR[c]) - alpha * (WR[c] - WL[c]);
+        out[c] = f[c] + alpha * UL[c];
+        out[K + c] = fv[c] + alpha * VL[c];
+        out[2 * K + c] = fw[c] + alpha * WL[c];
+    }
+    F.side(UR, VR, WR, f, fv, fw);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        out[c] = (out[c] + f[c]) - alpha * UR[c];
+        out[K + c] = (out[K + c] + fv[c]) - alpha * VR[c];
+        out[2 * K + c] = (out[2 * K + c] + fw[c]) - alpha * WR[c];
     }
 }
 
 // Workgroups per CU, as the LDS of the face and flux arrays allows them (they
 // grow with Q and with the width of T); the register allocation follows.
-// Stage 1, which reads no U^n and no saved hats, fits four FP32-face
-// workgroups in 128 registers; the other stages would spill there.
+// Stages 1 and 2 fit four FP32-face workgroups in 128 registers (the edge
+// flux accumulates one side at a time); stage 3, which also gathers the wave
+// speeds, would spill there.
 template <int P, int Q, int mode> constexpr int stage2d_min_blocks() {
-    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : (mode == MODE_S1 ? 4 : 3));
+    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : (mode == MODE_S1 || mode == MODE_S2 ? 4 : 3));
 }
 
 template <int P, int K, int Q, int FLUX, int mode>
