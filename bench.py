@@ -32,12 +32,12 @@ VEC_TFLOPS = 78.6              # MI355X vector FP64, = non-packed FP32 (FMA coun
 # FP operations per cell-stage of the 2D Euler stage (Q = 2): the FP
 # instruction counters of the stage kernel (FMA = 2, other FP instructions 1)
 # restricted to output-producing lanes and rows (profiles/stage2d_euler2048.md)
-ALU_FLOP_PER_CELL_STAGE = 2658.0
+ALU_FLOP_PER_CELL_STAGE = 2706.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) for the kernel sources of this hash; any change of
 # the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "dd33cfd9ecd86079"
-PROFILED_TRAFFIC = {"f32acc64": 821.9e6, "f64": 1243.6e6}
+PROFILED_SOURCES = "8090d9fc491abc8a"
+PROFILED_TRAFFIC = {"f32acc64": 824.1e6, "f64": 1243.6e6}
 
 
 def kernel_sources_hash() -> str:
