@@ -133,3 +133,23 @@ def test_fullsize_steps_as_benchmarked_equal_single_steps(workload):
             outs.append(h.get_state(0))
     (a, ta), (b, tb) = outs
     assert ta == tb and np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec,tol", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-6)])
+def test_fullsize_step_sampled_three_gauss_points(workload, prec, tol):
+    """The paper's three Gauss points per edge at the full size: one step on
+    the sampled windows (tile and segment boundaries, corners)."""
+    spec, st = workload
+    cfg = hw.default_config(2, precision=prec, gauss_q=3, cfl=0.5)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        dt = h.step(want_dt=True)[0]
+        out, _ = h.get_state(0)
+    p = oproblem(spec, cfg)
+    O.set_threads(os.cpu_count() or 1)
+    ax, ay = O.alpha(p, st)
+    S = natural_scales(spec, st)
+    for (i0, j0, wi, wj) in windows(N):
+        ref = O.step_window(p, st, ax, ay, dt, i0, j0, wi, wj)
+        got = out[:, :, j0:j0 + wj, i0:i0 + wi]
+        assert scaled_err(got, ref, S) < tol, (i0, j0, scaled_err(got, ref, S))
