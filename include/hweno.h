@@ -131,11 +131,18 @@ void hweno_default_config(int32_t dim, hweno_config* cfg);
 size_t hweno_workspace_bytes(const hweno_problem* probs, int32_t nprob,
                              const hweno_config* cfg);
 
-/* Creates a handle for nprob problems (all of the same dim and flux).
+/* Creates a handle for nprob problems (all of the same dim and flux), each
+ * an instance of u_t + div F(u) = 0 on a uniform Cartesian mesh (Sec. 1,
+ * eq. hyperbolic-conservation-laws; the meshes of Sec. 2.1 and 2.2) with the
+ * scheme parameters of Sec. 2 (linear weights of eq. rewrite /
+ * eq. rewrite-2D, eps of the nonlinear weights, Gauss points per edge) and
+ * the CFL number of Sec. 3.
  * workspace: device memory of at least hweno_workspace_bytes() bytes that the
  * handle uses for all its buffers (it stays owned by the caller and must
  * outlive the handle), or NULL to let the handle allocate its own.
- * hip_stream: the hipStream_t every call is ordered on (NULL = null stream).
+ * hip_stream: the hipStream_t every call is ordered on; NULL makes the
+ * handle create a private blocking stream of its own (a stream that HIP
+ * graphs can be captured on), destroyed with the handle.
  * Errors: ERR_ARG (mismatched dims or flux, nx/ny out of range, gauss_q not
  * 2 or 3, linear weights not all positive or |sum - 1| > 1e-12, eps <= 0,
  * cfl <= 0), ERR_OOM, ERR_HIP. */
@@ -143,7 +150,11 @@ int hweno_create(const hweno_problem* probs, int32_t nprob, const hweno_config* 
                  void* workspace, size_t ws_bytes, void* hip_stream, hweno_handle** out);
 
 /* Uploads the state of problem prob (layout above, double) and sets its time
- * to t.  Synchronising.  Errors: ERR_ARG (bad prob index or NULL src). */
+ * to t: the initial data u(x, 0) = u0(x) of Sec. 1 as the cell averages and
+ * derivative averages the scheme evolves (Sec. 2.1: u-bar and v-bar;
+ * Sec. 2.2: u-bar, v-bar, w-bar), or any later state.  The wave speeds of
+ * the state are reduced afresh by the next step.  Synchronising.
+ * Errors: ERR_ARG (bad prob index or NULL src). */
 int hweno_set_state(hweno_handle* h, int32_t prob, const double* src,
                     int32_t src_on_device, double t);
 
@@ -162,7 +173,10 @@ int hweno_rhs(hweno_handle* h, int32_t prob, double* L_out, double* Uhat_out,
               int32_t on_device);
 
 /* Lax-Friedrichs speeds (alpha_x, alpha_y) of the current cell averages of
- * problem prob: max |f'(u)| (Euler: |velocity| + sound speed) over its cells.
+ * problem prob: max |f'(u)| over its cells, the speed of the global
+ * Lax-Friedrichs flux (Sec. 2.1, the flux of the semi-discrete scheme;
+ * Sec. 2.2, separate speeds for the x- and y-fluxes); for Euler the
+ * spectral radius |velocity| + sound speed of the flux Jacobian.
  * Synchronising.  Errors: ERR_NONFINITE if a cell is not admissible. */
 int hweno_alpha(hweno_handle* h, int32_t prob, double* ax, double* ay);
 
@@ -185,7 +199,10 @@ int hweno_step(hweno_handle* h, const double* dt_in, double* dt_out);
  * nsteps < 0, ERR_STATE before set_state. */
 int hweno_steps(hweno_handle* h, int32_t nsteps);
 
-/* Advances every problem to its t_end with the CFL rule.  Synchronising.
+/* Advances every problem to its t_end with SSP-RK3 steps (Sec. 2.1 Step 4,
+ * Sec. 2.2 Step 4) whose length follows the CFL rule of Sec. 3 (dt = CFL
+ * dx / alpha in 1D, CFL / (alpha_x/dx + alpha_y/dy) in 2D, dx^e with the
+ * configured exponent), the last step clipped onto t_end.  Synchronising.
  * steps_out (may be NULL) receives the number of steps of the longest run.
  * Errors: ERR_NONFINITE (names the problem and cell), ERR_STATE. */
 int hweno_run_to_time(hweno_handle* h, int64_t* steps_out);
