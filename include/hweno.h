@@ -245,6 +245,42 @@ typedef struct {
 
 int hweno_timed_steps(hweno_handle* h, int32_t nsteps, hweno_timing* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): one step
+ * of one problem as hweno_step takes it (same kernels, same bits), on a
+ * state the caller holds in device memory, with no handle.
+ *   prob, cfg   as for hweno_create (one problem); the step is clipped onto
+ *               prob->t_end, and none is taken when t >= t_end;
+ *   state_in    device, the boundary layout above (double), read only;
+ *   state_out   device, same layout; receives the new state (when no step
+ *               is taken, the input as stored in the configured precision);
+ *               may equal state_in;
+ *   t           the state's time;
+ *   dt_in       > 0: the step to take (still clipped); otherwise the CFL
+ *               rule on the state's own wave speeds;
+ *   dt_out      device double or NULL: the step taken, 0 if none;
+ *   bad_out     device int64 or NULL: -1, or the first cell (j*nx + i) of
+ *               the input that is not admissible (then no step is taken);
+ *   hip_stream  the stream every launch is ordered on (NULL: null stream).
+ * Every intermediate buffer (three stage states, saved hats, problem table,
+ * work lists) lives in one fixed device array of HWENO_NOALLOC_SCRATCH_BYTES
+ * per GPU, which each GPU the library runs on holds until the process ends;
+ * its address is looked up once per device, on the first call there.  The
+ * call allocates nothing and copies nothing between host and device: it only
+ * enqueues kernels.  A problem needs, per cell, 3 K (su + D sd) + K D sd
+ * bytes (K components, D = dim, su = 8 except 4 for F32, sd = 8 for F64 and
+ * 4 otherwise) plus a few KB: e.g. at most about 190 000 cells of 2D Euler
+ * in F64, 299 000 in F32_ACC64.
+ * Every call on a GPU shares that GPU's array and leaves its contents behind
+ * (each call rewrites what it reads first): calls that overlap on one GPU,
+ * on different streams or threads, race and give undefined results.
+ * Errors (hweno_last_error(NULL)): ERR_ARG as hweno_create, NULL states, or a
+ * problem larger than the array; ERR_HIP. */
+#define HWENO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hweno_step_noalloc(const hweno_problem* prob, const hweno_config* cfg,
+                       const double* state_in, double* state_out, double t, double dt_in,
+                       double* dt_out, int64_t* bad_out, void* hip_stream);
+
 int hweno_destroy(hweno_handle* h);
 
 /* Text of the last error on h, or of the last failed hweno_create on this

@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 SOURCES = ["stage2d_f64.hip", "stage2d_f32.hip", "stage2d_acc64.hip", "stage2d_kahan.hip",
            "stage2d_char.hip", "stage2d.hip",
-           "stage1d.hip", "control.hip", "api.cpp"]
+           "stage1d.hip", "control.hip", "noalloc.hip", "api.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -106,6 +106,61 @@ static int tiles_2d(int nx, int ny, int rows) {
 }
 
 static int validate(const hweno_problem* probs, int32_t nprob, const hweno_config* cfg,
+                    hweno_handle* h);
+
+namespace hweno {
+int validate_problems(const hweno_problem* probs, int32_t nprob, const hweno_config* cfg) {
+    return validate(probs, nprob, cfg, nullptr);
+}
+
+int thread_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_create_error = buf;
+    return code;
+}
+
+Scheme scheme_of(const hweno_problem& p0, const hweno_config& cfg) {
+    Scheme s{};
+    for (int m = 0; m < 5; ++m) s.gam[m] = cfg.gamma_lin[m];
+    s.eps = cfg.eps;
+    s.gas_gamma = p0.gas_gamma;
+    s.adv[0] = p0.adv[0];
+    s.adv[1] = p0.adv[1];
+    s.weights = cfg.weights;
+    s.Q = cfg.gauss_q;
+    s.charwise = cfg.characteristic && p0.flux == F_EULER;
+    s.smoothness = cfg.smoothness;
+    return s;
+}
+
+ProbDev probdev_of(const hweno_problem& pr, const hweno_config& cfg, int64_t off_u,
+                   int64_t off_d) {
+    ProbDev d;
+    std::memset(&d, 0, sizeof d);
+    d.nx = pr.nx;
+    d.ny = pr.ny;
+    d.bc_x = pr.bc_x;
+    d.bc_y = pr.dim == 2 ? pr.bc_y : HWENO_PERIODIC;
+    d.off_u = off_u;
+    d.off_d = off_d;
+    d.dx = (pr.xhi - pr.xlo) / pr.nx;
+    d.dy = pr.dim == 2 ? (pr.yhi - pr.ylo) / pr.ny : 1.0;
+    d.inv_dx = 1.0 / d.dx;
+    d.inv_dy = 1.0 / d.dy;
+    d.dxe = std::pow(d.dx, cfg.dt_exponent);
+    d.dye = std::pow(d.dy, cfg.dt_exponent);
+    d.t = 0.0;
+    d.t_end = pr.t_end;
+    d.bad_cell = INT64_MAX;
+    return d;
+}
+}  // namespace hweno
+
+static int validate(const hweno_problem* probs, int32_t nprob, const hweno_config* cfg,
                     hweno_handle* h) {
     if (!probs || nprob <= 0 || !cfg) return fail(h, HWENO_ERR_ARG, "no problems or no config");
     const int dim = probs[0].dim, flux = probs[0].flux;
@@ -329,16 +384,7 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     h->stage_elems = L.stage_elems;
     h->nchunks = L.nchunks;
 
-    // scheme constants
-    for (int m = 0; m < 5; ++m) h->sch.gam[m] = cfg->gamma_lin[m];
-    h->sch.eps = cfg->eps;
-    h->sch.gas_gamma = probs[0].gas_gamma;
-    h->sch.adv[0] = probs[0].adv[0];
-    h->sch.adv[1] = probs[0].adv[1];
-    h->sch.weights = cfg->weights;
-    h->sch.Q = cfg->gauss_q;
-    h->sch.charwise = cfg->characteristic && h->flux == F_EULER;
-    h->sch.smoothness = cfg->smoothness;
+    h->sch = scheme_of(probs[0], *cfg);
 
     // problem table
     h->h_probs.resize(nprob);
@@ -347,23 +393,7 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     std::vector<Chunk> chunks;
     for (int q = 0; q < nprob; ++q) {
         const hweno_problem& pr = probs[q];
-        ProbDev& d = h->h_probs[q];
-        std::memset(&d, 0, sizeof d);
-        d.nx = pr.nx;
-        d.ny = pr.ny;
-        d.bc_x = pr.bc_x;
-        d.bc_y = h->dim == 2 ? pr.bc_y : HWENO_PERIODIC;
-        d.off_u = ou;
-        d.off_d = od;
-        d.dx = (pr.xhi - pr.xlo) / pr.nx;
-        d.dy = h->dim == 2 ? (pr.yhi - pr.ylo) / pr.ny : 1.0;
-        d.inv_dx = 1.0 / d.dx;
-        d.inv_dy = 1.0 / d.dy;
-        d.dxe = std::pow(d.dx, cfg->dt_exponent);
-        d.dye = std::pow(d.dy, cfg->dt_exponent);
-        d.t = 0.0;
-        d.t_end = pr.t_end;
-        d.bad_cell = INT64_MAX;
+        h->h_probs[q] = probdev_of(pr, *cfg, ou, od);
         const int64_t nc = (int64_t)pr.nx * pr.ny;
         h->ncell[q] = nc;
         ou += (int64_t)h->K * nc;

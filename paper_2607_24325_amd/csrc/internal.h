@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/hweno.h"
+
 namespace hweno {
 
 // Arithmetic modes (values match HWENO_F64 ... HWENO_F32_KAHAN).
@@ -133,5 +135,16 @@ hipError_t launch_finish(ProbDev* probs, StepCtl* ctl, int nprob, hipStream_t s)
 // ext[((var*K + c)*ny + j)*nx + i]) and the internal planes of buf.
 hipError_t launch_pack(int prec, int to_internal, double* ext, StateBuf buf, int64_t off_u,
                        int64_t off_d, int K, int nvar, int64_t ncell, hipStream_t s);
+
+// --- host helpers of the C ABI (api.cpp) --------------------------------
+// Checks problems and configuration (ERR_ARG with the reason as the
+// thread's last error).
+int validate_problems(const hweno_problem* probs, int32_t nprob, const hweno_config* cfg);
+// Sets the thread's last error (hweno_last_error(NULL)); returns code.
+int thread_error(int code, const char* fmt, ...);
+Scheme scheme_of(const hweno_problem& p0, const hweno_config& cfg);
+// Per-problem table entry (static fields; time 0, speeds unknown).
+ProbDev probdev_of(const hweno_problem& pr, const hweno_config& cfg, int64_t off_u,
+                   int64_t off_d);
 
 }  // namespace hweno

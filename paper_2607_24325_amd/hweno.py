@@ -60,7 +60,7 @@ _lib = None
 EXPORTS = ["hweno_default_config", "hweno_workspace_bytes", "hweno_create", "hweno_set_state",
            "hweno_get_state", "hweno_rhs", "hweno_alpha", "hweno_step", "hweno_steps", "hweno_run_to_time",
            "hweno_sync", "hweno_get_tuning", "hweno_set_tuning", "hweno_autotune",
-           "hweno_timed_steps", "hweno_destroy", "hweno_last_error"]
+           "hweno_timed_steps", "hweno_step_noalloc", "hweno_destroy", "hweno_last_error"]
 
 
 def lib():
@@ -90,6 +90,9 @@ def lib():
         L.hweno_set_tuning.argtypes = [H, P(hweno_tuning)]
         L.hweno_autotune.argtypes = [H, P(hweno_tuning)]
         L.hweno_timed_steps.argtypes = [H, C.c_int32, P(hweno_timing)]
+        L.hweno_step_noalloc.argtypes = [P(hweno_problem), P(hweno_config), C.c_void_p,
+                                         C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
         L.hweno_destroy.argtypes = [H]
         L.hweno_last_error.argtypes = [H]
         L.hweno_last_error.restype = C.c_char_p
@@ -267,3 +270,27 @@ class Handle:
             if lib().hweno_get_state(self.h, i, None, 0, C.byref(t)) == ERR_NONFINITE:
                 bad.append(i)
         return bad
+
+
+def _dev_ptr(a):
+    """Device address of a torch CUDA tensor, or an address given as an int."""
+    if a is None or isinstance(a, int):
+        return a
+    assert a.is_cuda and a.is_contiguous()
+    return a.data_ptr()
+
+
+def step_noalloc(spec, cfg: hweno_config, state_in, state_out, t: float = 0.0,
+                 dt: float = 0.0, dt_out=None, bad_out=None, stream=None) -> None:
+    """hweno_step_noalloc: one step of one problem on device memory (float64
+    states in the boundary layout; dt_out one float64 and bad_out one int64
+    on the device, or None), given as torch CUDA tensors or raw device
+    addresses.  Only enqueues on `stream`."""
+    for a in (state_in, state_out):
+        assert isinstance(a, int) or str(a.dtype) == "torch.float64"
+    p = problem(spec)
+    rc = lib().hweno_step_noalloc(C.byref(p), C.byref(cfg), _dev_ptr(state_in),
+                                  _dev_ptr(state_out), float(t), float(dt), _dev_ptr(dt_out),
+                                  _dev_ptr(bad_out), stream)
+    if rc != OK:
+        raise HwenoError(rc, lib().hweno_last_error(None).decode())
