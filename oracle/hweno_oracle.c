@@ -18,6 +18,10 @@
 #endif
 
 static int g_threads = 0;
+/* Loops over fewer work items than this run on one thread: the fork and
+ * join of a parallel region would cost more than the loop (every result is
+ * the same either way; iterations are independent). */
+#define OMP_MIN_WORK 4096
 
 void orc_set_threads(int n) { g_threads = n; }
 
@@ -761,7 +765,7 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
         double* um = (double*)malloc(sizeof(double) * nc * K * 4); /* u(+1/2),u(-1/2),ux(+),ux(-) */
         double* vh = (double*)malloc(sizeof(double) * nc * K);
         if (!um || !vh) { free(um); free(vh); return -5; }
-#pragma omp parallel for num_threads(nthreads) schedule(static)
+#pragma omp parallel for num_threads(nthreads) schedule(static) if (nc * K >= OMP_MIN_WORK)
         for (int t = 0; t < nc; ++t) {
             int i = xa - 1 + t;
             double s[12], w[8];
@@ -834,7 +838,7 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
     double* hat = (double*)malloc(sizeof(double) * (size_t)rw * rh * K * 2);
     if (!poly || !hat) { free(poly); free(hat); return -5; }
     double* polyY = poly + (size_t)rw * rh * K * 15;
-#pragma omp parallel for num_threads(nthreads) schedule(static)
+#pragma omp parallel for num_threads(nthreads) schedule(static) if (rw * rh >= OMP_MIN_WORK)
     for (int tj = 0; tj < rh; ++tj) {
         int j = ya - 1 + tj;
         for (int ti = 0; ti < rw; ++ti) {
@@ -879,7 +883,7 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
     double* FY = (double*)calloc(nfy, sizeof(double));
     if (!FX || !FY) { free(poly); free(hat); free(FX); free(FY); return -5; }
 
-#pragma omp parallel for num_threads(nthreads) schedule(static)
+#pragma omp parallel for num_threads(nthreads) schedule(static) if (rw * rh >= OMP_MIN_WORK)
     for (int tj = 1; tj < rh - 1; ++tj) {
         for (int e = 0; e < nxe_edges; ++e) {
             /* edge between grown-rect columns e and e+1, row tj */
@@ -916,7 +920,7 @@ static int eval_operator(const orc_problem* p, ext_t* U, double ax, double ay, i
                     FX[(((size_t)(tj - 1) * nxe_edges + e) * K + c) * 3 + s] = dy * acc[s][c];
         }
     }
-#pragma omp parallel for num_threads(nthreads) schedule(static)
+#pragma omp parallel for num_threads(nthreads) schedule(static) if (rw * rh >= OMP_MIN_WORK)
     for (int e = 0; e < nye_edges; ++e) {
         for (int ti = 1; ti < rw - 1; ++ti) {
             const double* PB = polyY + (((size_t)e * rw + ti) * K) * 15;       /* below */
