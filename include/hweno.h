@@ -210,23 +210,40 @@ int hweno_run_to_time(hweno_handle* h, int64_t* steps_out);
 /* Waits for the handle's stream and reports a pending device-side error. */
 int hweno_sync(hweno_handle* h);
 
-/* Kernel tiling of the stage kernels.  tile_rows: rows one workgroup
- * marches through in 2D (8..1024) or cells per tile in 1D (fixed by the
- * kernel, ignored); grid_blocks: workgroups of the persistent launch (0 =
- * one per tile); use_graph: capture one step as a HIP graph (1) or launch
- * eagerly (0).  Changing any of these never changes a result bit. */
+/* Launch configuration of the stage kernels.  tile_rows: rows one
+ * workgroup marches through in 2D (8..1024) or cells per tile in 1D (fixed
+ * by the kernel, ignored); grid_blocks: workgroups of the persistent launch
+ * (0 = one per tile); use_graph: capture steps as HIP graphs (1) or launch
+ * eagerly (0); variant: register allocation of the 2D Euler stage kernels
+ * (0: for the occupancy their face arrays comfortably allow; 1: for one
+ * workgroup more per CU, with fewer registers; ignored elsewhere); source
+ * (read only): where the configuration came from (HWENO_TUNED_*).  Changing
+ * any of these never changes a result bit. */
 typedef struct {
     int32_t tile_rows;
     int32_t grid_blocks;
     int32_t use_graph;
+    int32_t variant;
+    int32_t source;
     int32_t reserved;
 } hweno_tuning;
 
+enum { HWENO_TUNED_DEFAULT = 0, HWENO_TUNED_BY_CALLER = 1, HWENO_TUNED_BY_TIMING = 2,
+       HWENO_TUNED_FROM_CACHE = 3 };
+
 int hweno_get_tuning(const hweno_handle* h, hweno_tuning* t);
+/* Errors: ERR_ARG for values out of range. */
 int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
 
-/* Times candidate tilings on the handle's current state (which it restores)
- * and keeps the fastest.  Synchronising.  best (may be NULL) receives it. */
+/* Times candidate launch configurations (segment heights, persistent grid
+ * sizes, register variants; the caller's use_graph is kept) on a few steps
+ * of the handle's current state, which it restores, and keeps the fastest.
+ * If the environment variable HWENO_TUNING_CACHE names a file, a
+ * configuration stored there for the same device, dimension, flux,
+ * precision, Gauss points, reconstruction and size class (problems and
+ * cells to the nearest power of two) is applied without timing, and a newly
+ * timed winner is appended (one JSON object per line).  Synchronising.
+ * best (may be NULL) receives the configuration in use afterwards. */
 int hweno_autotune(hweno_handle* h, hweno_tuning* best);
 
 /* Per-kernel timing of nsteps steps (CFL rule), launched eagerly on the

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -414,6 +415,8 @@ static int setup(hweno_handle* h, const hweno_problem* probs, int32_t nprob,
     h->tun.tile_rows = 32;
     h->tun.grid_blocks = 0;
     h->tun.use_graph = 1;
+    h->tun.variant = 0;
+    h->tun.source = HWENO_TUNED_DEFAULT;
     return build_tiles(h);
 }
 
@@ -556,7 +559,8 @@ static StageArgs stage_args(hweno_handle* h, int mode) {
 
 static hipError_t launch_stage(hweno_handle* h, int mode, const StageArgs& a) {
     if (h->dim == 1) return launch_stage1d(h->prec, h->flux, mode, a, h->tun.grid_blocks, h->stream);
-    return launch_stage2d(h->prec, h->flux, h->cfg.gauss_q, mode, a, h->tun.grid_blocks, h->stream);
+    return launch_stage2d(h->prec, h->flux, h->cfg.gauss_q, mode, h->tun.variant, a,
+                          h->tun.grid_blocks, h->stream);
 }
 
 static int alpha_all(hweno_handle* h) {
@@ -796,24 +800,128 @@ extern "C" int hweno_get_tuning(const hweno_handle* h, hweno_tuning* t) {
     return HWENO_OK;
 }
 
-extern "C" int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t) {
-    if (!h || !t) return HWENO_ERR_ARG;
+static int apply_tuning(hweno_handle* h, const hweno_tuning* t, int source) {
     if (t->tile_rows < 8 || t->tile_rows > 1024)
         return fail(h, HWENO_ERR_ARG, "tile_rows must lie in [8, 1024]");
     if (t->grid_blocks < 0) return fail(h, HWENO_ERR_ARG, "grid_blocks must be >= 0");
+    if (t->use_graph != 0 && t->use_graph != 1) return fail(h, HWENO_ERR_ARG, "use_graph must be 0 or 1");
+    if (t->variant != 0 && t->variant != 1) return fail(h, HWENO_ERR_ARG, "variant must be 0 or 1");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     drop_graph(h);
     h->tun = *t;
-    h->tun.reserved = 0;
+    h->tun.source = source;
     return build_tiles(h);
 }
 
-// Times a few steps per candidate tiling from the same saved state and keeps
-// the fastest; the state, times and counters are restored afterwards.
+extern "C" int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t) {
+    if (!h || !t) return HWENO_ERR_ARG;
+    return apply_tuning(h, t, HWENO_TUNED_BY_CALLER);
+}
+
+// Tuning cache: one JSON object per line,
+//   {"key": "<arch>|cu<n>|dim<d>|flux<f>|prec<p>|q<Q>|char<c>|p2^<a>|c2^<b>",
+//    "tile_rows": r, "grid_blocks": g, "variant": v, "step_ms": t}
+// (problems and cells rounded to powers of two); the last line with a key wins.
+static std::string tuning_key(hweno_handle* h) {
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+        ncu = prop.multiProcessorCount;
+    }
+    int64_t cells = 0;
+    for (int64_t c : h->ncell) cells += c;
+    auto lg = [](double x) { return (int)std::lround(std::log2(std::max(1.0, x))); };
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|cu%d|dim%d|flux%d|prec%d|q%d|char%d|p2^%d|c2^%d", arch.c_str(), ncu,
+             h->dim, h->flux, h->prec, h->dim == 2 ? h->cfg.gauss_q : 0, h->sch.charwise,
+             lg((double)h->nprob), lg((double)cells));
+    return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, hweno_tuning* t) {
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    const std::string want = "\"key\": \"" + key + "\"";
+    while (std::fgets(line, sizeof line, f)) {
+        if (!std::strstr(line, want.c_str())) continue;
+        int r = 0, g = 0, v = 0;
+        const char* pr = std::strstr(line, "\"tile_rows\":");
+        const char* pg = std::strstr(line, "\"grid_blocks\":");
+        const char* pv = std::strstr(line, "\"variant\":");
+        if (pr && pg && pv && std::sscanf(pr, "\"tile_rows\": %d", &r) == 1 &&
+            std::sscanf(pg, "\"grid_blocks\": %d", &g) == 1 &&
+            std::sscanf(pv, "\"variant\": %d", &v) == 1 && r >= 8 && r <= 1024 && g >= 0 &&
+            (v == 0 || v == 1)) {
+            t->tile_rows = r;
+            t->grid_blocks = g;
+            t->variant = v;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const hweno_tuning& t,
+                        double ms) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;   // a cache that cannot be written is not an error
+    std::fprintf(f,
+                 "{\"key\": \"%s\", \"tile_rows\": %d, \"grid_blocks\": %d, \"variant\": %d, "
+                 "\"step_ms\": %.6f}\n",
+                 key.c_str(), t.tile_rows, t.grid_blocks, t.variant, ms);
+    std::fclose(f);
+}
+
+// The launch configurations the tuner times.  2D: segment heights (the halo
+// rows recomputed per segment against the number of workgroups), one
+// workgroup per tile or a persistent grid of 2-4 per CU, and for the Euler
+// kernels both register variants.  1D: tiles are fixed by the kernel; one
+// workgroup per tile or a persistent grid.
+static std::vector<hweno_tuning> tuning_candidates(hweno_handle* h) {
+    std::vector<hweno_tuning> cands;
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int graph = h->tun.use_graph;
+    if (h->dim == 1) {
+        for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cands.push_back({64, g, graph, 0, 0, 0});
+        return cands;
+    }
+    const int nvar = (h->flux == F_EULER && !h->sch.charwise) ? 2 : 1;
+    for (int v = 0; v < nvar; ++v)
+        for (int rows : {16, 24, 32, 48, 64})
+            for (int g : {0, 2 * ncu, 3 * ncu, 4 * ncu}) cands.push_back({rows, g, graph, v, 0, 0});
+    return cands;
+}
+
+// Times a few steps per candidate launch configuration from the same saved
+// state and keeps the fastest; the state, times and counters are restored
+// afterwards.  With HWENO_TUNING_CACHE naming a file, a configuration stored
+// there for the same key is taken without timing, and a timed winner is
+// appended to it.
 extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     if (!h) return HWENO_ERR_ARG;
     int rc = all_set(h);
     if (rc) return rc;
+    const char* cache = std::getenv("HWENO_TUNING_CACHE");
+    const std::string key = tuning_key(h);
+    if (cache && *cache) {
+        hweno_tuning t = h->tun;
+        if (cache_lookup(cache, key, &t)) {
+            rc = apply_tuning(h, &t, HWENO_TUNED_FROM_CACHE);
+            if (rc) return rc;
+            if (best) *best = h->tun;
+            return HWENO_OK;
+        }
+    }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     std::vector<ProbDev> saved_probs;
     rc = read_probs(h, saved_probs);
@@ -836,23 +944,14 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
         return HWENO_OK;
     };
     HIP_TRY(h, hipMemcpyAsync(save, h->U[0].u, ub + db, hipMemcpyDeviceToDevice, h->stream));
-    std::vector<hweno_tuning> cands;
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (h->dim == 1) {
-        for (int g : {0, 2 * ncu, 4 * ncu, 8 * ncu}) cands.push_back({64, g, 1, 0});
-    } else {
-        for (int rows : {16, 24, 32, 48, 64, 128})
-            for (int g : {0, 2 * ncu}) cands.push_back({rows, g, 1, 0});
-    }
+    const std::vector<hweno_tuning> cands = tuning_candidates(h);
     hweno_tuning keep = h->tun, win = h->tun;
     double best_ms = 1e300;
     hipEvent_t e0, e1;
     HIP_TRY(h, hipEventCreate(&e0));
     HIP_TRY(h, hipEventCreate(&e1));
     for (const hweno_tuning& c : cands) {
-        rc = hweno_set_tuning(h, &c);
+        rc = apply_tuning(h, &c, HWENO_TUNED_BY_TIMING);
         if (rc) break;
         rc = launch_step(h);  // warm-up (and graph build)
         if (rc) break;
@@ -875,13 +974,14 @@ extern "C" int hweno_autotune(hweno_handle* h, hweno_tuning* best) {
     int rc2 = restore();
     (void)hipFree(save);
     if (rc) {
-        hweno_set_tuning(h, &keep);
+        apply_tuning(h, &keep, keep.source);
         return rc;
     }
     if (rc2) return rc2;
-    rc = hweno_set_tuning(h, &win);
+    rc = apply_tuning(h, &win, HWENO_TUNED_BY_TIMING);
     if (rc) return rc;
-    if (best) *best = win;
+    if (cache && *cache) cache_store(cache, key, win, best_ms / 3.0);
+    if (best) *best = h->tun;
     return HWENO_OK;
 }
 

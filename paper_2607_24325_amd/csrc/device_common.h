@@ -289,6 +289,81 @@ __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, doubl
     if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad, seen_x, seen_y);
 }
 
+// Wave speeds of the cell averages a stage-3 launch has just written for one
+// 2D tile (rows [j0, jend), output columns [i0, i0 + STRIP_OUT) within the
+// problem), gathered after the tile's march by every wave of the workgroup:
+// wave w reads a contiguous share of the rows in order, lane l column i0 + l,
+// and evaluates wave_speed exactly, except where the four averages equal, bit
+// for bit, those this lane evaluated last (the same speeds, already in its
+// maxima: regions of constant state cost one evaluation per share).  The
+// workgroup's maxima and first non-admissible cell are folded into the
+// problem's slots for the next step.  out_u: the problem's u-bar planes of
+// the state written; the march's stores must be visible (a barrier after
+// them); s_mx, s_my, s_bad: LDS of one entry per wave.  Not inlined: its
+// FP64 divisions would otherwise raise the register allocation of the
+// whole march.
+template <class TU, int FLUX, int K>
+__device__ __attribute__((noinline)) void gather_tile_speeds(const TU* out_u, uint32_t plane, int nx,
+                                                   int i0, int j0, int jend, ProbDev& P,
+                                                   const Scheme& sch, double* s_mx, double* s_my,
+                                                   long long* s_bad) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t seen_x = 0, seen_y = 0;
+    if (threadIdx.x == 0) {   // read early: the gather covers the latency
+        seen_x = peek_slot(&P.ax_next);
+        seen_y = peek_slot(&P.ay_next);
+    }
+    const bool col = lane < STRIP_OUT && i0 + lane < nx;
+    const int per = (jend - j0 + nw - 1) / nw;
+    const int ra = j0 + w * per, rb = min(jend, ra + per);
+    double mx = 0.0, my = 0.0;
+    long long bad = LLONG_MAX;
+    double prev[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) prev[k] = __builtin_nan("");   // equal to nothing
+    for (int j = ra; j < rb; ++j) {
+        const uint32_t idx = (uint32_t)(j * nx + i0 + (col ? lane : 0));
+        double u[K];
+        bool same = true;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            u[k] = (double)plane_at(out_u + k * plane, idx);
+            same = same && u[k] == prev[k];
+        }
+        same = same || !col;
+        if (!__all(same) && !same) {
+            double sx, sy;
+            if (wave_speed<FLUX, 2, K>(u, sch, sx, sy)) {
+                mx = fmax(mx, sx);
+                my = fmax(my, sy);
+            } else {
+                const long long b = (long long)j * nx + i0 + lane;
+                bad = b < bad ? b : bad;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) prev[k] = u[k];
+        }
+    }
+    mx = wave_max_d(mx);
+    my = wave_max_d(my);
+    if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
+    if (lane == 0) {
+        s_mx[w] = mx;
+        s_my[w] = my;
+        s_bad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < nw; ++v) {
+            mx = fmax(mx, s_mx[v]);
+            my = fmax(my, s_my[v]);
+            bad = s_bad[v] < bad ? s_bad[v] : bad;
+        }
+        publish_reduced(P, mx, my, bad, seen_x, seen_y);
+    }
+}
+
 // --------------------------------------- classical smoothness indicator ---
 //
 // The indicator the paper prints for comparison with its own (eq.
@@ -458,15 +533,9 @@ template <class T, int K> struct Eigen {
 //
 // omega~_m = gamma_m (1 + tau^2 / D_m), omega = omega~ / sum (eq.
 // nonlinear-weights, eq. nonlinear-weights-2D), with D_m = beta_m + eps or
-// beta_m^2 + eps, tau = mean_m |beta_0 - beta_m|.
-template <class T, int M>
-__device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s, int squared,
-                                                  T* omega) {
-    if (s.weights == W_LINEAR) {
-#pragma unroll
-        for (int m = 0; m <= M; ++m) omega[m] = (T)s.gam[m];
-        return;
-    }
+// beta_m^2 + eps (SQ), tau = mean_m |beta_0 - beta_m|.
+template <class T, int M, bool SQ>
+__device__ __forceinline__ void nonlinear_weights_form(const T* beta, const Scheme& s, T* omega) {
     T tau = 0;
 #pragma unroll
     for (int m = 1; m <= M; ++m) tau += fabs(beta[0] - beta[m]);
@@ -476,13 +545,28 @@ __device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s
     T wt[M + 1], sum = 0;
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
-        const T den = squared ? beta[m] * beta[m] + eps : beta[m] + eps;
+        const T den = SQ ? beta[m] * beta[m] + eps : beta[m] + eps;
         wt[m] = (T)s.gam[m] * ((T)1 + tau2 * rcp(den));
         sum += wt[m];
     }
     const T inv = rcp(sum);
 #pragma unroll
     for (int m = 0; m <= M; ++m) omega[m] = wt[m] * inv;
+}
+
+// The form is chosen per launch (a branch on a wave-uniform value, so only
+// one of them is executed).
+template <class T, int M>
+__device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s, int squared,
+                                                  T* omega) {
+    if (s.weights == W_LINEAR) {
+#pragma unroll
+        for (int m = 0; m <= M; ++m) omega[m] = (T)s.gam[m];
+    } else if (squared) {
+        nonlinear_weights_form<T, M, true>(beta, s, omega);
+    } else {
+        nonlinear_weights_form<T, M, false>(beta, s, omega);
+    }
 }
 
 }  // namespace hweno

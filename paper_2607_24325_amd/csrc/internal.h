@@ -112,8 +112,11 @@ struct StageArgs {
 // --- launchers (defined in the .hip files) ------------------------------
 hipError_t launch_stage1d(int prec, int flux, int mode, const StageArgs& a, int grid,
                           hipStream_t s);
-hipError_t launch_stage2d(int prec, int flux, int Q, int mode, const StageArgs& a, int grid,
-                          hipStream_t s);
+// variant: register variant of the Euler stage kernels (0 or 1; see
+// stage2d_min_blocks), ignored for the scalar laws and the characteristic
+// kernel.
+hipError_t launch_stage2d(int prec, int flux, int Q, int mode, int variant, const StageArgs& a,
+                          int grid, hipStream_t s);
 // all_problems: zero the speeds of every problem (queries), or only of those
 // whose speeds are not current (time stepping).
 // Which problems a speed reset / reduction covers: every problem (after

@@ -171,7 +171,7 @@ extern "C" int hweno_step_noalloc(const hweno_problem* prob, const hweno_config*
         a.tile_offset = 0;
         a.sch = sch;
         if (dim == 1) NA_TRY(launch_stage1d(prec, flux, mode, a, 0, s));
-        else NA_TRY(launch_stage2d(prec, flux, cfg->gauss_q, mode, a, 0, s));
+        else NA_TRY(launch_stage2d(prec, flux, cfg->gauss_q, mode, 0, a, 0, s));
     }
     NA_TRY(launch_finish(probs, ctl, 1, s));
     NA_TRY(launch_pack(prec, 0, state_out, U[0], 0, 0, K, nvar, ncell, s));

@@ -187,27 +187,37 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
     }
 }
 
-// Workgroups per CU, as the LDS of the face and flux arrays allows them (they
-// grow with Q and with the width of T); the register allocation follows.
-// Stages 1 and 2 fit four FP32-face workgroups in 128 registers (the edge
-// flux accumulates one side at a time); stage 3, which also gathers the wave
-// speeds, would spill there.
-template <int P, int Q, int mode> constexpr int stage2d_min_blocks() {
-    return P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : (mode == MODE_S1 || mode == MODE_S2 ? 4 : 3));
+// Workgroups per CU the register allocation is made for (launch bounds).
+// Variant 0: the occupancy the face arrays and registers comfortably allow
+// (every stage fits four FP32-face workgroups in 128 registers, the edge
+// flux accumulating one side at a time and stage 3's speed gather being a
+// call of its own after the march); variant 1: one workgroup more per CU,
+// which caps the registers lower (the compiler may spill).  The tuner picks.
+template <int P, int Q, int mode, int V> constexpr int stage2d_min_blocks() {
+    return V + (P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : 4));
 }
 
-template <int P, int K, int Q, int FLUX, int mode>
-__global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) stage2d_kernel(StageArgs a) {
+template <int P, int K, int Q, int FLUX, int mode, int V>
+__global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>())) stage2d_kernel(StageArgs a) {
     using TU = typename PrecT<P>::TU;
     using TD = typename PrecT<P>::TD;
     using T = typename PrecT<P>::T;
     using TA = typename PrecT<P>::TA;
     constexpr int NF = Q * 3 * K;  // face values per lane and face (all components)
+    // Face values at the Gauss points, entry (mu*3 + v)*K + comp, v = value,
+    // d/dxi, d/deta.  The doubled edge fluxes of node mu, entry sk*K + comp
+    // (sk = u, v, w flux), are written over the face values they come from:
+    // x-edge l over sxR[mu*3*K + .][l], y-edge l over syB[mu*3*K + .][l].
+    // Only the thread of that edge point reads those face values, and it
+    // reads them all before it writes; the residual of component c reads
+    // only entries of component c, which the next row's reconstruction
+    // rewrites in the same wave, so no other wave can overwrite a flux
+    // before it is read.
     __shared__ T sxR[NF][64], sxL[NF][64], syB[NF][64], syT[NF][64];
-    __shared__ T sFX[Q][3 * K][64], sFY[Q][3 * K][64];
-    __shared__ double snew[K][64];   // stage 3: new cell averages of the output row
-    __shared__ double smx[64], smy[64];   // stage 3: per-lane maxima of the wave speeds
-    __shared__ long long sbad[64];        // stage 3: per-lane first non-admissible cell
+    auto FX = [&](int mu, int k, int l) -> T& { return sxR[mu * 3 * K + k][l]; };
+    auto FY = [&](int mu, int k, int l) -> T& { return syB[mu * 3 * K + k][l]; };
+    __shared__ double smx[K], smy[K];  // stage 3: per-wave maxima of the wave speeds
+    __shared__ long long sbad[K];      // stage 3: per-wave first non-admissible cell
 
     const int lane = threadIdx.x & 63;
     // component of this wave (uniform: the plane pointers stay in SGPRs)
@@ -219,20 +229,11 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
     const Tile2D* tiles = (const Tile2D*)a.tiles + a.tile_offset;
 
     // Stage 3 also gathers the wave speeds of the state it writes (for the
-    // next step's flux and time step): one wave per output row reads the four
-    // new averages of each cell from LDS one barrier after they were written
-    // and keeps per-lane maxima in LDS (no registers live across the march).
-    // The gathering wave rotates with the row: wave w of every resident
-    // workgroup runs on SIMD w, so a fixed wave would load one SIMD of the CU
-    // with all the gathers.  The maxima start cleared; the wave that
-    // publishes a tile's maxima clears them again for the next tile (ordered
-    // before that tile's first gather by its first barrier).
+    // next step's flux and time step), after each tile's march: the gather
+    // reads the tile's new averages back (they are in the L2 the stores
+    // went through) with every wave, so the march itself carries no extra
+    // registers and no wave waits for another's gather at a barrier.
     constexpr bool fuse_alpha = mode == MODE_S3;
-    if (fuse_alpha && c == 0) {
-        smx[lane] = 0.0;
-        smy[lane] = 0.0;
-        sbad[lane] = LLONG_MAX;
-    }
 
     for (int tix = blockIdx.x; tix < a.ntiles; tix += gridDim.x) {
         const Tile2D tile = tiles[tix];
@@ -285,23 +286,6 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
         };
         const int j0 = tile.j0, jend = tile.j0 + tile.nrows;  // outputs j0..jend-1
 
-        auto gather_wave = [](int row) { return (int)((unsigned)row % (unsigned)K); };
-        auto gather_speeds = [&](int row) {
-            if (c == gather_wave(row) && out_col) {
-                double u[K];
-#pragma unroll
-                for (int k = 0; k < K; ++k) u[k] = snew[k][lane];
-                double sx, sy;
-                if (wave_speed<FLUX, 2, K>(u, sch, sx, sy)) {
-                    smx[lane] = fmax(smx[lane], sx);
-                    smy[lane] = fmax(smy[lane], sy);
-                } else {
-                    const long long idx = (long long)row * nx + gi;
-                    if (idx < sbad[lane]) sbad[lane] = idx;
-                }
-            }
-        };
-
         TU um, u0, up, un_;
         TD vm, v0, vp, vn_, wm, w0, wp, wn_;
         load_row(j0 - 2, um, vm, wm);
@@ -339,7 +323,26 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
                     for (int v = 0; v < 3; ++v) syT[(mu * 3 + v) * K + c][lane] = ytop[mu][v];
             }
             T q[17];
-            {
+            if constexpr (sizeof(T) == 4) {
+                // Single precision: the column's own differences and the
+                // differences of the side neighbours' averages from the centre
+                // are rounded once from the wide averages; a corner is the sum
+                // of the neighbour column's own difference and that column's
+                // centre difference, which the compiler forms in one add with a
+                // DPP lane shift on its first operand.
+                const TU uc = u0;
+                const T dm = (T)(um - uc), dp = (T)(up - uc);
+                const T dl = (T)(from_left(u0) - uc), dr = (T)(from_right(u0) - uc);
+                q[0] = from_left(dm) + dl;
+                q[1] = dm;
+                q[2] = from_right(dm) + dr;
+                q[3] = dl;
+                q[4] = (T)0;
+                q[5] = dr;
+                q[6] = from_left(dp) + dl;
+                q[7] = dp;
+                q[8] = from_right(dp) + dr;
+            } else {
                 const TU uc = u0;
                 q[0] = (T)(from_left(um) - uc);
                 q[1] = (T)(um - uc);
@@ -350,6 +353,8 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
                 q[6] = (T)(from_left(up) - uc);
                 q[7] = (T)(up - uc);
                 q[8] = (T)(from_right(up) - uc);
+            }
+            {
                 q[9] = (T)from_left(v0);
                 q[10] = (T)from_right(v0);
                 q[11] = (T)vm;
@@ -393,7 +398,6 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
 
             if (r > j0 - 1) {
                 __syncthreads();  // A: face values of row r (and top faces of r-1) ready
-                if (fuse_alpha && r > j0 + 1) gather_speeds(r - 2);
                 // ---- F: edge fluxes ---------------------------------------
                 for (int sl = threadIdx.x; sl < 2 * Q * 64; sl += 64 * K) {
                     const int kind = sl / (Q * 64);
@@ -413,7 +417,7 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
                             }
                             lf_edge<T, FLUX, K, 0>(FXf, UL, VL, WL, UR, VR, WR, ax, out);
 #pragma unroll
-                            for (int k = 0; k < 3 * K; ++k) sFX[mu][k][l] = out[k];
+                            for (int k = 0; k < 3 * K; ++k) FX(mu, k, l) = out[k];
                         }
                     } else {            // y-edge between rows r-1 and r, column l
 #pragma unroll
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
                         }
                         lf_edge<T, FLUX, K, 1>(FYf, UL, VL, WL, UR, VR, WR, ay, out);
 #pragma unroll
-                        for (int k = 0; k < 3 * K; ++k) sFY[mu][k][l] = out[k];
+                        for (int k = 0; k < 3 * K; ++k) FY(mu, k, l) = out[k];
                     }
                 }
                 __syncthreads();  // B: fluxes ready
@@ -442,9 +446,9 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
 #pragma unroll
                     for (int mu = 0; mu < Q; ++mu) {
                         const T w = (T)(0.5 * Gauss<Q>::w(mu));   // fluxes are stored doubled
-                        fr += w * sFX[mu][sk * K + c][lane];
-                        fl += w * sFX[mu][sk * K + c][lane > 0 ? lane - 1 : 0];
-                        g += w * sFY[mu][sk * K + c][lane];
+                        fr += w * FX(mu, sk * K + c, lane);
+                        fl += w * FX(mu, sk * K + c, lane > 0 ? lane - 1 : 0);
+                        g += w * FY(mu, sk * K + c, lane);
                     }
                     if (sk == 0) {
                         xdu = (TA)fr - (TA)fl;
@@ -484,9 +488,7 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
                                 plane_at(Ow, oo) = (TD)((T)0.75 * hwr + (T)0.25 * (hat_prev[1] + dtt * Lw));
                             } else {
                                 const TA third = (TA)(1.0 / 3.0), two3 = (TA)(2.0 / 3.0);
-                                const TU nu = (TU)(third * unr + two3 * (ucur + dta * Lu));
-                                plane_at(Ou, oo) = nu;
-                                snew[c][lane] = (double)nu;
+                                plane_at(Ou, oo) = (TU)(third * unr + two3 * (ucur + dta * Lu));
                                 plane_at(Ov, oo) = (TD)((T)(1.0 / 3.0) * hvr +
                                               (T)(2.0 / 3.0) * (hat_prev[0] + dtt * Lv));
                                 plane_at(Ow, oo) = (TD)((T)(1.0 / 3.0) * hwr +
@@ -510,20 +512,45 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode>())) st
             vm = v0; v0 = vp; vp = vn_;
             wm = w0; w0 = wp; wp = wn_;
         }
-        __syncthreads();  // LDS reuse by the next tile
-        if (fuse_alpha && c == gather_wave(jend - 1)) {
-            // the slots are read first: the last row's gather covers the read
-            ProbDev& Pw = a.probs[tile.prob];
-            const uint64_t seen_x = peek_slot(&Pw.ax_next), seen_y = peek_slot(&Pw.ay_next);
-            gather_speeds(jend - 1);
-            const double mxl = smx[lane], myl = smy[lane];
-            const long long badl = sbad[lane];
-            smx[lane] = 0.0;
-            smy[lane] = 0.0;
-            sbad[lane] = LLONG_MAX;
-            publish_next_speeds(Pw, mxl, myl, badl, seen_x, seen_y);
-        }
+        __syncthreads();  // LDS reuse by the next tile; the tile's stores are visible
+        if (fuse_alpha)
+            gather_tile_speeds<TU, FLUX, K>((const TU*)a.out.u + off_u, (uint32_t)plane, nx, tile.i0,
+                                            j0, jend, a.probs[tile.prob], sch, smx, smy, sbad);
     }
+}
+
+// Launches the stage kernel of one precision: Euler in either register
+// variant, the scalar laws in variant 0.
+template <int P, int K, int Q, int FLUX, int V>
+void stage2d_launch_modes(int mode, const StageArgs& a, int grid, hipStream_t s) {
+    constexpr int threads = 64 * K;
+    switch (mode) {
+        case MODE_RHS: stage2d_kernel<P, K, Q, FLUX, MODE_RHS, V><<<grid, threads, 0, s>>>(a); break;
+        case MODE_S1: stage2d_kernel<P, K, Q, FLUX, MODE_S1, V><<<grid, threads, 0, s>>>(a); break;
+        case MODE_S2: stage2d_kernel<P, K, Q, FLUX, MODE_S2, V><<<grid, threads, 0, s>>>(a); break;
+        default: stage2d_kernel<P, K, Q, FLUX, MODE_S3, V><<<grid, threads, 0, s>>>(a); break;
+    }
+}
+
+template <int P>
+hipError_t stage2d_launch_prec(int flux, int Q, int mode, int variant, const StageArgs& a,
+                               int grid, hipStream_t s) {
+    if (flux == F_EULER) {
+        if (Q == 2) {
+            if (variant) stage2d_launch_modes<P, 4, 2, F_EULER, 1>(mode, a, grid, s);
+            else stage2d_launch_modes<P, 4, 2, F_EULER, 0>(mode, a, grid, s);
+        } else {
+            if (variant) stage2d_launch_modes<P, 4, 3, F_EULER, 1>(mode, a, grid, s);
+            else stage2d_launch_modes<P, 4, 3, F_EULER, 0>(mode, a, grid, s);
+        }
+    } else if (flux == F_BURGERS) {
+        if (Q == 2) stage2d_launch_modes<P, 1, 2, F_BURGERS, 0>(mode, a, grid, s);
+        else stage2d_launch_modes<P, 1, 3, F_BURGERS, 0>(mode, a, grid, s);
+    } else {
+        if (Q == 2) stage2d_launch_modes<P, 1, 2, F_ADV, 0>(mode, a, grid, s);
+        else stage2d_launch_modes<P, 1, 3, F_ADV, 0>(mode, a, grid, s);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace hweno

@@ -42,7 +42,11 @@ class hweno_config(C.Structure):
 
 class hweno_tuning(C.Structure):
     _fields_ = [("tile_rows", C.c_int32), ("grid_blocks", C.c_int32),
-                ("use_graph", C.c_int32), ("reserved", C.c_int32)]
+                ("use_graph", C.c_int32), ("variant", C.c_int32), ("source", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+TUNED_DEFAULT, TUNED_BY_CALLER, TUNED_BY_TIMING, TUNED_FROM_CACHE = 0, 1, 2, 3
 
 
 class hweno_timing(C.Structure):
@@ -236,7 +240,7 @@ class Handle:
         self._check(lib().hweno_get_tuning(self.h, C.byref(t)))
         return t
 
-    def set_tuning(self, tile_rows=None, grid_blocks=None, use_graph=None):
+    def set_tuning(self, tile_rows=None, grid_blocks=None, use_graph=None, variant=None):
         t = self.tuning()
         if tile_rows is not None:
             t.tile_rows = tile_rows
@@ -244,12 +248,17 @@ class Handle:
             t.grid_blocks = grid_blocks
         if use_graph is not None:
             t.use_graph = use_graph
+        if variant is not None:
+            t.variant = variant
         self._check(lib().hweno_set_tuning(self.h, C.byref(t)))
 
     def autotune(self) -> hweno_tuning:
         t = hweno_tuning()
         self._check(lib().hweno_autotune(self.h, C.byref(t)))
         return t
+
+    def tuned_from_cache(self) -> bool:
+        return self.tuning().source == TUNED_FROM_CACHE
 
     def timed_steps(self, nsteps: int, allow_nonfinite: bool = False) -> hweno_timing:
         """Per-kernel timing of nsteps eager steps.  With allow_nonfinite, a

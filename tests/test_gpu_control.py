@@ -88,6 +88,38 @@ def test_autotune_restores_state_and_speeds(steps_before):
     assert scaled_err(g, ref, natural_scales(spec, st)) < 1e-11
 
 
+def test_autotune_cache_and_eager_mode(tmp_path, monkeypatch):
+    """The tuner keeps the caller's eager mode in every candidate, stores its
+    winner in the cache file named by HWENO_TUNING_CACHE, and a second
+    handle of the same class takes the stored configuration without timing;
+    the tuned and cached runs give the bits of the default run."""
+    cache = tmp_path / "tuning.jsonl"
+    monkeypatch.setenv("HWENO_TUNING_CACHE", str(cache))
+    cfg = _cfg()
+    spec, st = W.quadrant_vortex_2d(96, seed=7)
+    outs = []
+    for mode in ("default", "timed", "cached"):
+        with hw.Handle([spec], cfg) as h:
+            h.set_state(0, st)
+            if mode != "default":
+                h.set_tuning(use_graph=0)
+                t = h.autotune()
+                assert t.use_graph == 0
+                assert t.source == (hw.TUNED_BY_TIMING if mode == "timed" else hw.TUNED_FROM_CACHE)
+                assert h.tuning().source == t.source
+            for _ in range(3):
+                h.step()
+            outs.append(h.get_state(0)[0])
+            if mode == "timed":
+                timed = (t.tile_rows, t.grid_blocks, t.variant)
+            elif mode == "cached":
+                assert (t.tile_rows, t.grid_blocks, t.variant) == timed
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and '"tile_rows"' in lines[0] and "|dim2|flux2|" in lines[0]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+
+
 def test_light_step_counts_and_final_time():
     """Several problems with different end times run to their ends: every
     problem lands exactly on its t_end, and the step count equals the

@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import oproblem, plane_rel, l1_rel, natural_scales, scaled_err, rhs_scales
+from gpu_util import (l1_rel, l1_scaled, natural_scales, oproblem, plane_rel, rhs_scales,
+                      scaled_err)
 from paper_2607_24325_amd import hweno as hw
 from paper_2607_24325_amd import workloads as W
 
@@ -142,6 +143,12 @@ def test_2d_euler_step_reduced_precision(prec, tol):
         ax, ay = O.alpha(p, ref)
         ref = O.step(p, ref, ax, ay, dt)
     assert l1_rel(gpu[0], ref[0]) < tol, l1_rel(gpu[0], ref[0])
+    # every plane, the derivative averages included, in its natural scale
+    S = natural_scales(spec, st)
+    print(f"2D 96^2 three steps prec {prec}: L1 {l1_scaled(gpu, ref, S):.3e} "
+          f"max {scaled_err(gpu, ref, S):.3e}", flush=True)
+    assert l1_scaled(gpu, ref, S) < tol
+    assert scaled_err(gpu, ref, S) < 20 * tol
 
 
 @pytest.mark.parametrize("prec", [hw.F32, hw.F32_ACC64, hw.F32_KAHAN])
@@ -157,6 +164,11 @@ def test_1d_euler_step_reduced_precision(prec):
         ax, _ = O.alpha(p, ref)
         ref = O.step(p, ref, ax, 0.0, dt)
     assert l1_rel(gpu[0], ref[0]) < 2e-5
+    S = natural_scales(spec, st)
+    print(f"1D 600 five steps prec {prec}: L1 {l1_scaled(gpu, ref, S):.3e} "
+          f"max {scaled_err(gpu, ref, S):.3e}", flush=True)
+    assert l1_scaled(gpu, ref, S) < 2e-5
+    assert scaled_err(gpu, ref, S) < 4e-4
 
 
 @pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F32_KAHAN])
@@ -176,15 +188,18 @@ def test_mixed_precision_conserves_cell_average_totals(prec):
 
 # ------------------------------------------------ tiling and determinism --
 
-def test_results_independent_of_tiling_and_graphs():
+@pytest.mark.parametrize("prec", [hw.F64, hw.F32_ACC64])
+def test_results_independent_of_tiling_and_graphs(prec):
     """Bitwise-identical results for every segment height, persistent grid
-    size and graph/eager launch: no races, no order dependence."""
+    size, register variant and graph/eager launch: no races, no order
+    dependence."""
     spec, st = W.quadrant_vortex_2d(128, seed=2)
-    cfg = hw.default_config(2, precision=hw.F64, gauss_q=2)
+    cfg = hw.default_config(2, precision=prec, gauss_q=2)
     outs = []
-    for rows, grid, graph in [(64, 0, 1), (16, 0, 1), (128, 0, 0), (32, 37, 1), (8, 256, 0)]:
+    for rows, grid, graph, var in [(64, 0, 1, 0), (16, 0, 1, 0), (128, 0, 0, 0), (32, 37, 1, 0),
+                                   (8, 256, 0, 0), (32, 0, 1, 1), (24, 512, 1, 1), (48, 0, 0, 1)]:
         with _one(spec, st, cfg) as h:
-            h.set_tuning(tile_rows=rows, grid_blocks=grid, use_graph=graph)
+            h.set_tuning(tile_rows=rows, grid_blocks=grid, use_graph=graph, variant=var)
             for _ in range(3):
                 h.step()
             outs.append(h.get_state(0)[0])
