@@ -3,23 +3,30 @@
 Workload: 2D Euler (gamma 1.4) on periodic [0,1]^2, 2048 x 2048 cells, 12
 unknowns per cell (average, x- and y-moment of 4 conserved variables), two
 Gauss points per edge, CFL 0.5, seeded quadrant states plus an isentropic
-vortex (seed 7).  A step is one full SSP-RK3 step (wave-speed reduction, dt,
-three fused stage kernels, time update) of the whole grid, inputs resident
-in HBM.  Metric: cell-stage updates per second (3 per cell per step).
+vortex (seed 7).  A step is one full SSP-RK3 step (dt, three fused stage
+kernels, time update; the wave speeds come from the previous step's stage 3)
+of the whole grid, inputs resident in HBM.  Metric: cell-stage updates per
+second (3 per cell per step).
 
 The single-precision-bulk path (FP32 reconstruction and fluxes, FP64 cell
-averages and flux differences) is the headline value; the FP64 path is
-measured beside it, with the L1 distance between the two after the timed
-steps.  The CPU oracle's own rate on the host cores is the reported
-baseline (the parity of both paths with the oracle at this size is checked
-by tests/test_gpu_fullsize.py).
+averages and flux differences) is the headline value, measured with the
+autotuned launch configuration (the library default is reported beside it);
+the FP64 path, the characteristic-variable path and the two batched
+workloads (4096 uneven 1D problems in FP32 bulk with FP64 averages; 256
+uneven 2D problems with Kahan-compensated averages) are measured beside it.
+Every result carries its error against the FP64 CPU oracle (first step on
+sampled windows or problems, and a whole run to t = 0.1 at 128^2) and the
+drift of its periodic totals over the timed steps.  The oracle's own rate on
+the host cores, one thread and all threads, is the reported baseline.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
+import threading
 import time
 
 import numpy as np
@@ -28,16 +35,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VEC_TFLOPS = 78.6              # MI355X vector FP64, = non-packed FP32 (FMA counted as 2)
-# FP operations per cell-stage of the 2D Euler stage (Q = 2): the FP
-# instruction counters of the stage kernel (FMA = 2, other FP instructions 1)
-# restricted to output-producing lanes and rows (profiles/stage2d_euler2048.md)
-ALU_FLOP_PER_CELL_STAGE = 2706.0
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
-# the copy calibration) for the kernel sources of this hash; any change of
-# the sources invalidates them (reported as null until measured again).
-PROFILED_SOURCES = "8090d9fc491abc8a"
-PROFILED_TRAFFIC = {"f32acc64": 824.1e6, "f64": 1243.6e6}
+# the copy calibration), and VALU wave-instructions per launch, for the
+# kernel sources of this hash; any change of the sources invalidates them
+# (reported as null until measured again).
+PROFILED_SOURCES = "0b8254c236520d13"
+PROFILED_TRAFFIC = {"f32acc64": 874.3e6, "f64": 1271.4e6}
+PROFILED_VALU = {"f32acc64": 148.5e6, "f64": 168.1e6}
+# the launch configuration (tile_rows, grid_blocks) those counters were taken
+# with: the halo re-reads depend on it
+PROFILED_LAUNCH = {"f32acc64": (48, 1024), "f64": (48, 0)}
 
 
 def kernel_sources_hash() -> str:
@@ -57,11 +64,106 @@ def algorithmic_bytes_per_cell_stage(K: int, D: int, su: int, sd: int) -> float:
     return (6 * S + 3 * H + 2 * K * su) / 3.0
 
 
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+# --------------------------------------------------------------- errors ---
+
+def natural_scales(spec, st):
+    """per (var, comp) plane: max |u-bar| for averages; for derivative means
+    the larger of their own max and the range of the averages over one cell"""
+    S = np.zeros((spec.nvar, spec.K))
+    for c in range(spec.K):
+        u = st[0, c]
+        rng = float(u.max() - u.min())
+        S[0, c] = np.abs(u).max()
+        for v in range(1, spec.nvar):
+            S[v, c] = max(np.abs(st[v, c]).max(), rng / (spec.dx if spec.dim == 1 else 1.0))
+    return np.where(S > 0, S, 1.0)
+
+
+def err_summary(got, ref, S):
+    """L1 (mean over cells) and L-inf of the difference, each plane in its
+    natural scale, worst plane; and the plain density L1"""
+    ax = tuple(range(2, ref.ndim))
+    d = np.abs(np.asarray(got, dtype=np.float64) - ref)
+    return {"l1": float((d.mean(axis=ax) / S).max()), "linf": float((d.max(axis=ax) / S).max()),
+            "rho_l1": float(d[0, 0].mean())}
+
+
+def drift(st0, st1):
+    """largest relative change of the periodic totals of the cell averages"""
+    t0 = st0[0].reshape(st0.shape[1], -1).sum(axis=1)
+    t1 = st1[0].reshape(st1.shape[1], -1).sum(axis=1)
+    return float((np.abs(t1 - t0) / np.abs(t0)).max())
+
+
+def windows(n):
+    return [(0, 0, 4, 4), (n - 4, n - 4, 4, 4), (n // 2 - 2, n // 2 - 2, 4, 4), (58, 62, 5, 5),
+            (n // 2 - 2, 7, 4, 4), (500 % n, 500 % n, 4, 4), (n - 6, n // 3, 6, 4)]
+
+
+def oproblem(O, spec, cfg):
+    return O.Problem(dim=spec.dim, flux=spec.flux, nx=spec.nx, ny=spec.ny, xlo=spec.xlo,
+                     xhi=spec.xhi, ylo=spec.ylo, yhi=spec.yhi, bc_x=spec.bc_x, bc_y=spec.bc_y,
+                     gas_gamma=spec.gas_gamma, adv=tuple(spec.adv), gauss_q=cfg.gauss_q,
+                     weights=cfg.weights,
+                     gamma_lin=tuple(cfg.gamma_lin)[:3 if spec.dim == 1 else 5], eps=cfg.eps,
+                     charwise=int(cfg.characteristic), smoothness=int(cfg.smoothness),
+                     alpha_stage=int(cfg.alpha_stage))
+
+
+def first_step_errors(O, spec, st, cfg, gpu1, dt, threads):
+    """the GPU's first step from the seeded state against the oracle's on
+    sampled windows (whole grid for small problems)"""
+    p = oproblem(O, spec, cfg)
+    O.set_threads(threads)
+    ax, ay = O.alpha(p, st)
+    odt = O.dt(p, ax, ay, cfg.cfl)
+    S = natural_scales(spec, st)
+    if spec.nx * spec.ny <= 300 * 300:
+        e = err_summary(gpu1, O.step(p, st, ax, ay, dt), S)
+        e["cells"] = "all"
+    else:
+        got, ref = [], []
+        for (i0, j0, wi, wj) in windows(spec.nx):
+            ref.append(O.step_window(p, st, ax, ay, dt, i0, j0, wi, wj).reshape(spec.nvar, spec.K, -1))
+            got.append(gpu1[:, :, j0:j0 + wj, i0:i0 + wi].reshape(spec.nvar, spec.K, -1))
+        e = err_summary(np.concatenate(got, axis=2), np.concatenate(ref, axis=2), S)
+        e["cells"] = f"{len(windows(spec.nx))} sampled windows"
+    e["dt_rel_diff"] = abs(dt - odt) / odt
+    return e
+
+
+# --------------------------------------------------------------- timing ---
+
 def timed_run(h, stream, steps: int, warmup: int, allow_nonfinite: bool = False):
     """Warm-up steps, then `steps` HIP-graph steps bracketed by events on the
     handle's stream (the step time; the library replays runs of 8 steps as
     one graph, built during the warm-up), then `steps` eagerly launched steps
-    with an event pair around every kernel (the per-kernel times)."""
+    with an event pair around every kernel, on the same stream (the
+    per-kernel times)."""
     import torch
     h.steps(warmup)
     torch.cuda.synchronize()
@@ -80,69 +182,220 @@ def timed_run(h, stream, steps: int, warmup: int, allow_nonfinite: bool = False)
     return ms_step, wall, tm
 
 
-def bench_batched(dim: int, prec: int, steps: int, warmup: int, dev, profile_only=False):
-    """Throughput of one of the batched workloads: 4096 uneven 1D Euler
-    problems (N ~ U{256..8192}, seed 1) or 256 uneven 2D Euler problems
-    (side ~ U{128..1024}, seed 11, Q = 2, CFL 0.5); one launch per RK stage
-    over every problem, per-problem dt."""
+def tuning_dict(t):
+    return {"tile_rows": t.tile_rows, "grid_blocks": t.grid_blocks, "use_graph": t.use_graph,
+            "variant": t.variant}
+
+
+def roofline(B, cells, stage_ms, key, kernel, tuning):
+    """HBM roofline of the dominant kernel from its algorithmic bytes and its
+    mean launch time measured with HIP events"""
+    achieved = B * cells / (stage_ms * 1e-3) / 1e9
+    same = (kernel_sources_hash() == PROFILED_SOURCES and
+            PROFILED_LAUNCH.get(key) == (tuning["tile_rows"], tuning["grid_blocks"]))
+    traffic = PROFILED_TRAFFIC.get(key) if same else None
+    valu = PROFILED_VALU.get(key) if same else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
+            "kernel": kernel, "kernel_ms": stage_ms, "cells_per_launch": cells,
+            "algorithmic_bytes_per_cell_stage": B,
+            "valu_wave_instructions_per_cell_stage": None if valu is None else valu / cells}
+
+
+def bench_single(hw, W, O, spec, st, prec, charwise, args, dev, stream, threads, tune):
+    """One 2048^2 path: first-step error against the oracle, the library
+    default launch configuration timed, then (if tune) the autotuned one."""
     import torch
-    from paper_2607_24325_amd import hweno as hw
-    from paper_2607_24325_amd import workloads as W
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5, characteristic=charwise)
+    ncell = spec.nx * spec.ny
+    ws = torch.empty(hw.Handle.workspace_bytes([spec], cfg), dtype=torch.uint8, device=dev)
+    h = hw.Handle([spec], cfg, workspace=ws, stream=stream.cuda_stream)
+    out = {}
+    try:
+        h.set_state(0, st)
+        dt1 = h.step(want_dt=True)[0]
+        gpu1, _ = h.get_state(0)
+        if O is not None:
+            out["errors_first_step"] = first_step_errors(O, spec, st, cfg, gpu1, dt1, threads)
+        del gpu1
+        if args.burn_in:
+            # the GPU idled while the host measured the oracle (or the
+            # process has just started): bring its clocks up before the
+            # first timed run
+            h.steps(args.burn_in)
+            torch.cuda.synchronize()
+        runs = [] if (tune and args.profile_only) else [("default", None)]
+        if tune:
+            runs.append(("tuned", "autotune"))
+        for name, how in runs:
+            h.set_state(0, st)
+            r = {}
+            if how == "autotune":
+                t0 = time.perf_counter()
+                tun = h.autotune()
+                r["autotune_s"] = time.perf_counter() - t0
+                r["from_cache"] = bool(h.tuned_from_cache())
+            r["tuning"] = tuning_dict(h.tuning())
+            ms_step, wall, tm = timed_run(h, stream, args.steps, args.warmup)
+            fin, t_now = h.get_state(0)
+            r.update({"value": 3.0 * ncell / (ms_step * 1e-3), "ms_per_step": ms_step,
+                      "wall_ms_per_step": wall * 1e3 / args.steps,
+                      "eager_ms_per_step": tm.total_ms / args.steps,
+                      "stage_kernel_ms": tm.stage_ms / tm.stage_launches,
+                      "alpha_ms_per_step": tm.alpha_ms / args.steps,
+                      "other_ms_per_step": tm.other_ms / args.steps,
+                      "t_reached": t_now, "conservation_drift": drift(st, fin)})
+            out[name] = r
+            del fin
+    finally:
+        h.close()
+        del ws
+    return out
+
+
+def bench_batched(hw, W, O, dim, prec, args, dev, stream, threads, tune):
+    """Throughput of one of the batched workloads: 4096 uneven 1D Euler
+    problems (N ~ U{256..8192}, seed 1, transmissive) or 256 uneven 2D Euler
+    problems (side ~ U{128..1024}, seed 11, mixed boundaries, Q = 2, CFL
+    0.5); one launch per RK stage over every problem, per-problem dt."""
+    import torch
     t0 = time.time()
     if dim == 1:
         entries = W.batched_1d(seed=1, nprob=4096)
         make = W.batched_1d_state
         cfg = hw.default_config(1, precision=prec)
-        K, su, sd = 3, 8, (8 if prec == hw.F64 else 4)
+        K = 3
     else:
         entries = W.batched_2d(seed=11, nprob=256)
         make = W.batched_2d_state
         cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
-        K, su, sd = 4, 8, (8 if prec == hw.F64 else 4)
+        K = 4
+    su = 4 if prec == hw.F32 else 8
+    sd = 8 if prec == hw.F64 else 4
     specs = [e[0] for e in entries]
     ncell = sum(s.nx * s.ny for s in specs)
+    states = [make(e) for e in entries]
     ws = torch.empty(hw.Handle.workspace_bytes(specs, cfg), dtype=torch.uint8, device=dev)
-    h = hw.Handle(specs, cfg, workspace=ws, stream=torch.cuda.current_stream(dev).cuda_stream)
-    for i, e in enumerate(entries):
-        h.set_state(i, make(e))
-    print(f"[bench] batched {dim}D: {len(specs)} problems, {ncell} cells, set up in "
-          f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    ms_step, _, tm = timed_run(h, torch.cuda.current_stream(dev), steps, warmup,
-                               allow_nonfinite=True)
-    stage_ms = tm.stage_ms / tm.stage_launches
-    # the scheme has no positivity limiter: a problem whose state becomes
-    # non-admissible is frozen by the library; its cells are not counted
-    failed = h.failed_problems()
-    live = ncell - sum(specs[i].nx * specs[i].ny for i in failed)
+    h = hw.Handle(specs, cfg, workspace=ws, stream=stream.cuda_stream)
+    r = {}
+    try:
+        for i, s in enumerate(states):
+            h.set_state(i, s)
+        print(f"[bench] batched {dim}D: {len(specs)} problems, {ncell} cells, set up in "
+              f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        # first step of the smallest problems against the oracle
+        dts = h.step(want_dt=True)
+        small = sorted(range(len(specs)), key=lambda i: specs[i].nx * specs[i].ny)[:4]
+        if O is not None:
+            errs = [first_step_errors(O, specs[i], states[i], cfg, h.get_state(i)[0], dts[i], threads)
+                    for i in small]
+            r["errors_first_step"] = {k: max(e[k] for e in errs) for k in ("l1", "linf", "rho_l1",
+                                                                            "dt_rel_diff")}
+            r["errors_first_step"]["cells"] = f"all cells of the {len(small)} smallest problems"
+        for i, s in enumerate(states):
+            h.set_state(i, s)
+        if tune:
+            tun = h.autotune()
+            r["tuning"] = tuning_dict(tun)
+        ms_step, _, tm = timed_run(h, stream, args.steps, args.warmup, allow_nonfinite=True)
+        stage_ms = tm.stage_ms / tm.stage_launches
+        # the scheme has no positivity limiter: a problem whose state becomes
+        # non-admissible is frozen by the library; its cells are not counted
+        failed = h.failed_problems()
+        live = ncell - sum(specs[i].nx * specs[i].ny for i in failed)
+        periodic = [i for i in range(len(specs)) if i not in failed and specs[i].bc_x == hw.PERIODIC
+                    and (dim == 1 or specs[i].bc_y == hw.PERIODIC)]
+        dr = [drift(states[i], h.get_state(i)[0]) for i in periodic[:32]]
+    finally:
+        h.close()
+        del ws
     B = algorithmic_bytes_per_cell_stage(K, dim, su, sd)
-    h.close()
-    del ws
-    r = {"problems": len(specs), "cells": ncell, "value": 3.0 * live / (ms_step * 1e-3),
-         "problems_frozen_nonadmissible": failed,
-         "unit": "cell-stage updates/s", "ms_per_step": ms_step, "stage_kernel_ms": stage_ms,
-         "bytes_per_cell_stage": B, "stage_hbm_frac": B * live / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-         "precision": "F32 bulk, FP64 cell averages" if prec != hw.F64 else "F64"}
+    r.update({"problems": len(specs), "cells": ncell, "value": 3.0 * live / (ms_step * 1e-3),
+              "problems_frozen_nonadmissible": failed, "unit": "cell-stage updates/s",
+              "ms_per_step": ms_step, "stage_kernel_ms": stage_ms, "bytes_per_cell_stage": B,
+              "stage_hbm_frac": B * live / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "conservation_drift": max(dr) if dr else None,
+              "conservation_drift_problems": f"{len(dr)} problems periodic on every axis"
+              if dr else "none (transmissive)",
+              "precision": {hw.F32_ACC64: "F32 bulk, FP64 cell averages",
+                            hw.F32_KAHAN: "F32 bulk, Kahan-compensated F32 cell averages",
+                            hw.F64: "F64", hw.F32: "F32"}[prec]})
     print(f"[bench] batched {dim}D: {ms_step:.3f} ms/step, stage {stage_ms:.3f} ms, "
           f"{r['value'] / 1e9:.2f} G cell-stage/s", file=sys.stderr, flush=True)
     return r
 
 
+# ------------------------------------------------------- oracle baseline ---
+
+def oracle_baseline(O, spec, st, cfg, ncores):
+    """The FP64 CPU oracle on bounded samples of the same workload: three
+    window steps of a band of rows (full width), on one thread and on every
+    host thread.  Rate = output cell-stage updates per second (the 6-cell
+    margins the window steps also compute are not counted)."""
+    p = oproblem(O, spec, cfg)
+    O.set_threads(ncores)
+    ax, ay = O.alpha(p, st)
+    dt = O.dt(p, ax, ay, cfg.cfl)
+    n = spec.nx
+    res = {}
+    for label, threads, rows in (("single_thread", 1, 64), ("all_threads", ncores, 512)):
+        O.set_threads(threads)
+        j0 = n // 2 - rows // 2
+        t0 = time.perf_counter()
+        for _ in range(3):
+            O.step_window(p, st, ax, ay, dt, 0, j0, n, rows)
+        el = time.perf_counter() - t0
+        res[label] = {"value": 3 * 3.0 * n * rows / el, "cores": O.get_threads(), "seconds": el,
+                      "sample": f"3 window steps of the {n}x{rows} band of rows {j0}..{j0 + rows - 1} "
+                                f"of the {n}x{n} workload"}
+    O.set_threads(0)
+    return res
+
+
+def final_time_reference(O, W, hw, n, threads, box):
+    """oracle run of the n^2 quadrant + vortex workload to t = 0.1 (run on a
+    thread while the GPU paths are measured)"""
+    spec, st = W.quadrant_vortex_2d(n, seed=7)
+    cfg = hw.default_config(2, precision=hw.F64, gauss_q=2, cfl=0.5)
+    O.set_threads(threads)
+    t0 = time.perf_counter()
+    ref, steps = O.run(oproblem(O, spec, cfg), st, 0.0, 0.1, 0.5)
+    box.update(spec=spec, st=st, ref=ref, steps=steps, seconds=time.perf_counter() - t0)
+
+
+def final_time_errors(hw, box, prec):
+    spec, st, ref = box["spec"], box["st"], box["ref"]
+    cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5)
+    with hw.Handle([spec], cfg) as h:
+        h.set_state(0, st)
+        steps = h.run_to_time()
+        out, t = h.get_state(0)
+    e = err_summary(out, ref, natural_scales(spec, st))
+    e.update({"steps": steps, "oracle_steps": box["steps"], "t": t,
+              "conservation_drift": drift(st, out),
+              "workload": f"quadrant+vortex {spec.nx}x{spec.ny} to t = 0.1, whole grid"})
+    return e
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2048)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--tune", action="store_true", help="run the autotuner first")
-    ap.add_argument("--precision", default="both", choices=["both", "f32acc64", "f64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (baseline and errors)")
+    ap.add_argument("--burn-in", type=int, default=200,
+                    help="untimed steps before a path's first measurement")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults only")
+    ap.add_argument("--precision", default="all", choices=["all", "f32acc64", "f64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB with a plain device copy (HBM counter scale)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workloads")
     ap.add_argument("--only-batched", type=int, default=0, choices=[0, 1, 2],
                     help="run only the batched 1D or 2D workload (profiling)")
     ap.add_argument("--profile-only", action="store_true",
-                    help="only run the timed steps (for profilers)")
+                    help="only the timed steps of the 2048^2 paths (for profilers)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path "
@@ -156,6 +409,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(dev)       # default priority
+    ncores = host_threads()
+    use_oracle = not (args.no_cpu or args.profile_only)
+    O = None
+    if use_oracle:
+        import oracle as O
+    # with --profile-only the tuner should find its choice in the cache that
+    # HWENO_TUNING_CACHE names (written by the full run), so that the
+    # profiled launches are the benchmarked ones and no candidate is timed
+    tune = not args.no_tune
     n = args.n
     t0 = time.time()
     spec, st = W.quadrant_vortex_2d(n, seed=7)
@@ -163,10 +426,10 @@ def main():
     ncell = n * n
 
     if args.only_batched:
-        r = bench_batched(args.only_batched, hw.F32_ACC64, args.steps, args.warmup, dev)
+        prec = hw.F32_ACC64 if args.only_batched == 1 else hw.F32_KAHAN
+        r = bench_batched(hw, W, None, args.only_batched, prec, args, dev, stream, ncores, False)
         print(json.dumps({f"batched_{args.only_batched}d": r}))
         return
-    results = {}
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -174,79 +437,75 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    runs = [("f32acc64", hw.F32_ACC64, 8, 4, 0), ("f64", hw.F64, 8, 8, 0)]
-    if args.precision != "both":
+
+    cpu = None
+    box, worker = {}, None
+    if use_oracle:
+        cfg64 = hw.default_config(2, precision=hw.F64, gauss_q=2, cfl=0.5)
+        base = oracle_baseline(O, spec, st, cfg64, ncores)
+        a = base["all_threads"]
+        cpu = {"value": a["value"], "unit": "cell-stage updates/s", "cores": a["cores"],
+               "kind": "oracle", "sample": a["sample"], "seconds": a["seconds"],
+               "cpu_model": cpu_model(), "single_thread": base["single_thread"]}
+        print(f"[bench] oracle: {a['value'] / 1e6:.3f} M cell-stage/s on {a['cores']} threads, "
+              f"{base['single_thread']['value'] / 1e6:.3f} M on one", file=sys.stderr, flush=True)
+        worker = threading.Thread(target=final_time_reference,
+                                  args=(O, W, hw, 128, max(1, ncores - 2), box), daemon=True)
+        worker.start()
+
+    runs = [("f32acc64", hw.F32_ACC64, 0), ("f64", hw.F64, 0)]
+    if args.precision != "all":
         runs = [r for r in runs if r[0] == args.precision]
     elif not args.profile_only:
-        # the same workload with the reconstruction in characteristic variables
-        runs.append(("f32acc64_characteristic", hw.F32_ACC64, 8, 4, 1))
-    for name, prec, su, sd, charwise in runs:
-        cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5, characteristic=charwise)
-        ws = torch.empty(hw.Handle.workspace_bytes([spec], cfg), dtype=torch.uint8, device=dev)
-        stream = torch.cuda.current_stream(dev)
-        h = hw.Handle([spec], cfg, workspace=ws, stream=stream.cuda_stream)
-        h.set_state(0, st)
-        entry = {}
-        if args.tune and not args.profile_only:
-            tun = h.autotune()
-            entry["tuning"] = {"tile_rows": tun.tile_rows, "grid_blocks": tun.grid_blocks}
-        ms_step, wall, tm = timed_run(h, stream, args.steps, args.warmup)
-        out, t_now = h.get_state(0)
-        stage_ms = tm.stage_ms / tm.stage_launches
-        B = algorithmic_bytes_per_cell_stage(4, 2, su, sd)
-        entry.update({
-            "value": 3.0 * ncell / (ms_step * 1e-3),
-            "ms_per_step": ms_step,
-            "wall_ms_per_step": wall * 1e3 / args.steps,
-            "eager_ms_per_step": tm.total_ms / args.steps,
-            "stage_kernel_ms": stage_ms,
-            "alpha_ms_per_step": tm.alpha_ms / args.steps,
-            "other_ms_per_step": tm.other_ms / args.steps,
-            "bytes_per_cell_stage": B,
-            "stage_hbm_gbs": B * ncell / (stage_ms * 1e-3) / 1e9,
-            "t_reached": t_now,
-            "state": out,
-        })
-        results[name] = entry
-        h.close()
-        del ws
-        print(f"[bench] {name}: {ms_step:.3f} ms/step, stage {stage_ms:.3f} ms, "
-              f"{entry['value'] / 1e9:.2f} G cell-stage/s", file=sys.stderr, flush=True)
+        runs.append(("f32acc64_characteristic", hw.F32_ACC64, 1))
+    results = {}
+    for name, prec, charwise in runs:
+        r = bench_single(hw, W, O, spec, st, prec, charwise, args, dev, stream,
+                         max(1, ncores - 2), tune)
+        results[name] = r
+        best = r.get("tuned", r.get("default"))
+        dflt = f" (default launch: {r['default']['ms_per_step']:.3f} ms/step)" if "default" in r else ""
+        print(f"[bench] {name}: {best['ms_per_step']:.3f} ms/step, stage "
+              f"{best['stage_kernel_ms']:.3f} ms, {best['value'] / 1e9:.2f} G cell-stage/s{dflt} "
+              f"tuning {best['tuning']}", file=sys.stderr, flush=True)
 
-    if args.profile_only or args.precision != "both":
+    if args.profile_only or args.precision != "all":
         for k, r in results.items():
-            r.pop("state", None)
             print(json.dumps({k: r}))
         return
-    main_r = results["f32acc64"]
-    f64_r = results["f64"]
-    l1_32_vs_64 = float(np.abs(main_r["state"][0] - f64_r["state"][0]).mean(axis=(1, 2)).max())
-    cpu = None
-    if not args.no_cpu and not args.profile_only:
-        import oracle as O
-        threads = os.cpu_count() or 1
-        O.set_threads(threads)
-        cfg = hw.default_config(2, precision=hw.F64, gauss_q=2, cfl=0.5)
-        p = O.Problem(dim=2, flux=O.EULER, nx=n, ny=n, gas_gamma=spec.gas_gamma, gauss_q=2,
-                      weights=cfg.weights, gamma_lin=tuple(cfg.gamma_lin), eps=cfg.eps)
-        ax, ay = O.alpha(p, st)
-        dt = O.dt(p, ax, ay, 0.5)
-        tc = time.perf_counter()
-        O.step(p, st, ax, ay, dt)
-        el = time.perf_counter() - tc
-        cpu = {"value": 3.0 * ncell / el, "unit": "cell-stage updates/s", "cores": O.get_threads(),
-               "kind": "oracle",
-               "sample": f"one full SSP-RK3 step of the {n}x{n} 2D Euler workload (FP64 oracle, "
-                         f"OpenMP over rows), {el:.1f}s"}
 
     batched = {}
     if not args.no_batched:
-        for d in (1, 2):
-            batched[f"batched_{d}d"] = bench_batched(d, hw.F32_ACC64, args.steps, args.warmup, dev)
-    B = main_r["bytes_per_cell_stage"]
-    achieved = main_r["stage_hbm_gbs"]
-    alu_tflops = ALU_FLOP_PER_CELL_STAGE * ncell / (main_r["stage_kernel_ms"] * 1e-3) / 1e12
-    traffic = PROFILED_TRAFFIC["f32acc64"] if kernel_sources_hash() == PROFILED_SOURCES else None
+        batched["batched_1d"] = bench_batched(hw, W, O, 1, hw.F32_ACC64, args, dev, stream,
+                                              max(1, ncores - 2), tune)
+        batched["batched_2d"] = bench_batched(hw, W, O, 2, hw.F32_KAHAN, args, dev, stream,
+                                              max(1, ncores - 2), tune)
+    final = None
+    if worker is not None:
+        worker.join()
+        final = {"f32acc64": final_time_errors(hw, box, hw.F32_ACC64),
+                 "f64": final_time_errors(hw, box, hw.F64),
+                 "oracle_seconds": box["seconds"]}
+
+    def path(r, key, kernel, su, sd):
+        best = r.get("tuned", r["default"])
+        B = algorithmic_bytes_per_cell_stage(4, 2, su, sd)
+        d = {"value": best["value"], "ms_per_step": best["ms_per_step"],
+             "stage_kernel_ms": best["stage_kernel_ms"], "tuning": best["tuning"],
+             "roofline": roofline(B, ncell, best["stage_kernel_ms"], key, kernel,
+                                  best["tuning"]),
+             "conservation_drift": best["conservation_drift"],
+             "errors_first_step": r.get("errors_first_step"),
+             "default_launch": {k: r["default"][k] for k in ("value", "ms_per_step",
+                                                             "stage_kernel_ms", "tuning")}}
+        if final is not None and key in final:
+            d["errors_final_time_128"] = final[key]
+        return d
+
+    main_r = path(results["f32acc64"], "f32acc64", "stage2d_kernel (F32_ACC64)", 8, 4)
+    f64_r = path(results["f64"], "f64", "stage2d_kernel (F64)", 8, 8)
+    ch = results["f32acc64_characteristic"]
+    ch_best = ch.get("tuned", ch["default"])
     line = {
         "metric": "cell-stage updates/s (2D Euler 2048^2, FP32 vs FP64) + % HBM peak + L1 err",
         "value": main_r["value"],
@@ -262,23 +521,19 @@ def main():
         "data": "synthetic (seeded quadrant states + isentropic vortex)",
         "config": {"workload": f"2D Euler {n}x{n} periodic, Q=2, CFL 0.5, quadrant+vortex seed 7",
                    "precision": "F32 bulk, FP64 cell averages and cell-average flux differences",
-                   "cells": ncell, "unknowns_per_cell": 12},
-        "roofline": {"bound": "alu", "achieved": alu_tflops, "peak": VEC_TFLOPS, "unit": "TFLOP/s",
-                     "frac": alu_tflops / VEC_TFLOPS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
-                     "kernel": "stage2d_kernel (F32_ACC64)",
-                     "algorithmic_flop_per_cell_stage": ALU_FLOP_PER_CELL_STAGE,
-                     "hbm_achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes_per_cell_stage": B},
-        "hbm_frac_fp64_path": f64_r["stage_hbm_gbs"] / HBM_PEAK_GBS,
-        "fp64_path": {"value": f64_r["value"], "ms_per_step": f64_r["ms_per_step"],
-                      "stage_kernel_ms": f64_r["stage_kernel_ms"],
-                      "bytes_per_cell_stage": f64_r["bytes_per_cell_stage"]},
-        "characteristic_path": {k: results["f32acc64_characteristic"][k]
-                                for k in ("value", "ms_per_step", "stage_kernel_ms")},
-        "l1_f32_vs_f64_after_timed_steps": l1_32_vs_64,
+                   "cells": ncell, "unknowns_per_cell": 12, "tuning": main_r["tuning"]},
+        "roofline": main_r["roofline"],
+        "errors_first_step": main_r["errors_first_step"],
+        "errors_final_time_128": main_r.get("errors_final_time_128"),
+        "conservation_drift": main_r["conservation_drift"],
+        "default_launch": main_r["default_launch"],
+        "fp64_path": f64_r,
+        "characteristic_path": {"value": ch_best["value"], "ms_per_step": ch_best["ms_per_step"],
+                                "stage_kernel_ms": ch_best["stage_kernel_ms"],
+                                "tuning": ch_best["tuning"],
+                                "errors_first_step": ch.get("errors_first_step"),
+                                "conservation_drift": ch_best["conservation_drift"]},
         "stage_kernel_ms": main_r["stage_kernel_ms"],
-        "tuning": main_r.get("tuning"),
         "cpu_baseline": cpu,
     }
     line.update(batched)
