@@ -289,62 +289,17 @@ __device__ __forceinline__ void publish_next_speeds(ProbDev& P, double mx, doubl
     if ((threadIdx.x & 63) == 0) publish_reduced(P, mx, my, bad, seen_x, seen_y);
 }
 
-// Wave speeds of the cell averages a stage-3 launch has just written for one
-// 2D tile (rows [j0, jend), output columns [i0, i0 + STRIP_OUT) within the
-// problem), gathered after the tile's march by every wave of the workgroup:
-// wave w reads a contiguous share of the rows in order, lane l column i0 + l,
-// and evaluates wave_speed exactly, except where the four averages equal, bit
-// for bit, those this lane evaluated last (the same speeds, already in its
-// maxima: regions of constant state cost one evaluation per share).  The
-// workgroup's maxima and first non-admissible cell are folded into the
-// problem's slots for the next step.  out_u: the problem's u-bar planes of
-// the state written; the march's stores must be visible (a barrier after
-// them); s_mx, s_my, s_bad: LDS of one entry per wave.  Not inlined: its
-// FP64 divisions would otherwise raise the register allocation of the
-// whole march.
-template <class TU, int FLUX, int K>
-__device__ __attribute__((noinline)) void gather_tile_speeds(const TU* out_u, uint32_t plane, int nx,
-                                                   int i0, int j0, int jend, ProbDev& P,
-                                                   const Scheme& sch, double* s_mx, double* s_my,
-                                                   long long* s_bad) {
+// Folds lane maxima of the wave speeds, and first non-admissible cells, of a
+// workgroup into the problem's slots: reduced over each wave, then over the
+// waves through LDS (s_mx, s_my, s_bad: one entry per wave) by thread 0,
+// which read the slots (seen_x, seen_y) before the values were formed.
+// Every thread of the workgroup calls it (it holds a barrier).
+__device__ __forceinline__ void publish_tile_speeds(ProbDev& P, double mx, double my,
+                                                    long long bad, uint64_t seen_x,
+                                                    uint64_t seen_y, double* s_mx, double* s_my,
+                                                    long long* s_bad) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint64_t seen_x = 0, seen_y = 0;
-    if (threadIdx.x == 0) {   // read early: the gather covers the latency
-        seen_x = peek_slot(&P.ax_next);
-        seen_y = peek_slot(&P.ay_next);
-    }
-    const bool col = lane < STRIP_OUT && i0 + lane < nx;
-    const int per = (jend - j0 + nw - 1) / nw;
-    const int ra = j0 + w * per, rb = min(jend, ra + per);
-    double mx = 0.0, my = 0.0;
-    long long bad = LLONG_MAX;
-    double prev[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) prev[k] = __builtin_nan("");   // equal to nothing
-    for (int j = ra; j < rb; ++j) {
-        const uint32_t idx = (uint32_t)(j * nx + i0 + (col ? lane : 0));
-        double u[K];
-        bool same = true;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            u[k] = (double)plane_at(out_u + k * plane, idx);
-            same = same && u[k] == prev[k];
-        }
-        same = same || !col;
-        if (!__all(same) && !same) {
-            double sx, sy;
-            if (wave_speed<FLUX, 2, K>(u, sch, sx, sy)) {
-                mx = fmax(mx, sx);
-                my = fmax(my, sy);
-            } else {
-                const long long b = (long long)j * nx + i0 + lane;
-                bad = b < bad ? b : bad;
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) prev[k] = u[k];
-        }
-    }
     mx = wave_max_d(mx);
     my = wave_max_d(my);
     if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
@@ -362,6 +317,72 @@ __device__ __attribute__((noinline)) void gather_tile_speeds(const TU* out_u, ui
         }
         publish_reduced(P, mx, my, bad, seen_x, seen_y);
     }
+}
+
+// Wave speeds of the cell averages a stage-3 launch has just written for one
+// 2D tile (rows [j0, jend), output columns [i0, i0 + STRIP_OUT) within the
+// problem), gathered after the tile's march by every wave of the workgroup:
+// wave w reads a contiguous share of the rows (they come from the L2 the
+// march's stores went through, or from HBM), lane l column i0 + l, and
+// evaluates wave_speed exactly for each cell; the workgroup's maxima and
+// first non-admissible cell are folded into the problem's slots for the next
+// step.  out_u: the problem's u-bar planes of the state written; the march's
+// stores must be visible (a barrier after them); s_mx, s_my, s_bad: LDS of
+// one entry per wave.  Not inlined: its FP64 division chains would otherwise
+// raise the register allocation of the whole march (and it stays within the
+// registers a call may use without saving any: no scratch).
+template <class TU, int FLUX, int K>
+__device__ __attribute__((noinline)) void gather_tile_speeds(const TU* out_u, uint32_t plane, int nx,
+                                                   int i0, int j0, int jend, ProbDev& P,
+                                                   const Scheme& sch, double* s_mx, double* s_my,
+                                                   long long* s_bad) {
+    // the planes are global memory (global rather than flat loads) at
+    // wave-uniform bases (scalar registers, 32-bit offsets per lane)
+    using GC = const __attribute__((address_space(1))) char;
+    auto uniform = [](uint64_t v) {
+        return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v) |
+               ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32);
+    };
+    GC* gp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) gp[k] = (GC*)uniform((uint64_t)out_u + (uint64_t)k * plane * sizeof(TU));
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t seen_x = 0, seen_y = 0;
+    if (threadIdx.x == 0) {   // read early: the gather covers the latency
+        seen_x = peek_slot(&P.ax_next);
+        seen_y = peek_slot(&P.ay_next);
+    }
+    const bool col = lane < STRIP_OUT && i0 + lane < nx;
+    const int per = (jend - j0 + nw - 1) / nw;
+    const int ra = j0 + w * per, rb = min(jend, ra + per);
+    const uint32_t ci = (uint32_t)(i0 + (col ? lane : 0));
+    double mx = 0.0, my = 0.0;
+    long long bad = LLONG_MAX;
+    for (int j = ra; j < rb; ++j) {
+        const uint32_t off = ((uint32_t)(j * nx) + ci) * (uint32_t)sizeof(TU);
+        double u[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            TU v;
+            if constexpr (sizeof(TU) == 8)
+                v = __builtin_bit_cast(TU, *(const __attribute__((address_space(1))) uint64_t*)(gp[k] + off));
+            else
+                v = __builtin_bit_cast(TU, *(const __attribute__((address_space(1))) uint32_t*)(gp[k] + off));
+            u[k] = (double)v;
+        }
+        if (col) {
+            double sx, sy;
+            if (wave_speed<FLUX, 2, K>(u, sch, sx, sy)) {
+                mx = fmax(mx, sx);
+                my = fmax(my, sy);
+            } else {
+                const long long b = (long long)j * nx + i0 + lane;
+                bad = b < bad ? b : bad;
+            }
+        }
+    }
+    publish_tile_speeds(P, mx, my, bad, seen_x, seen_y, s_mx, s_my, s_bad);
 }
 
 // --------------------------------------- classical smoothness indicator ---
@@ -533,19 +554,22 @@ template <class T, int K> struct Eigen {
 //
 // omega~_m = gamma_m (1 + tau^2 / D_m), omega = omega~ / sum (eq.
 // nonlinear-weights, eq. nonlinear-weights-2D), with D_m = beta_m + eps or
-// beta_m^2 + eps (SQ), tau = mean_m |beta_0 - beta_m|.
-template <class T, int M, bool SQ>
-__device__ __forceinline__ void nonlinear_weights_form(const T* beta, const Scheme& s, T* omega) {
+// beta_m^2 + eps (SQ = 1) or chosen per value (SQ = -1, from `squared`),
+// tau = mean_m |beta_0 - beta_m|.
+template <class T, int M, int SQ>
+__device__ __forceinline__ void nonlinear_weights_form(const T* beta, const Scheme& s, int squared,
+                                                       T* omega) {
     T tau = 0;
 #pragma unroll
     for (int m = 1; m <= M; ++m) tau += fabs(beta[0] - beta[m]);
     tau *= (T)(1.0 / M);
     const T tau2 = tau * tau;
     const T eps = (T)s.eps;
+    const bool sq = SQ < 0 ? squared != 0 : SQ != 0;
     T wt[M + 1], sum = 0;
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
-        const T den = SQ ? beta[m] * beta[m] + eps : beta[m] + eps;
+        const T den = sq ? beta[m] * beta[m] + eps : beta[m] + eps;
         wt[m] = (T)s.gam[m] * ((T)1 + tau2 * rcp(den));
         sum += wt[m];
     }
@@ -554,18 +578,22 @@ __device__ __forceinline__ void nonlinear_weights_form(const T* beta, const Sche
     for (int m = 0; m <= M; ++m) omega[m] = wt[m] * inv;
 }
 
-// The form is chosen per launch (a branch on a wave-uniform value, so only
-// one of them is executed).
-template <class T, int M>
+// The form is chosen per launch.  BRANCH: a branch on the wave-uniform flag,
+// each side with the form fixed at compile time (fewer instructions, more
+// code); else one copy selecting the denominator per value (fewer registers,
+// which bound the occupancy of the 1D kernel).
+template <class T, int M, bool BRANCH>
 __device__ __forceinline__ void nonlinear_weights(const T* beta, const Scheme& s, int squared,
                                                   T* omega) {
     if (s.weights == W_LINEAR) {
 #pragma unroll
         for (int m = 0; m <= M; ++m) omega[m] = (T)s.gam[m];
+    } else if (!BRANCH) {
+        nonlinear_weights_form<T, M, -1>(beta, s, squared, omega);
     } else if (squared) {
-        nonlinear_weights_form<T, M, true>(beta, s, omega);
+        nonlinear_weights_form<T, M, 1>(beta, s, squared, omega);
     } else {
-        nonlinear_weights_form<T, M, false>(beta, s, omega);
+        nonlinear_weights_form<T, M, 0>(beta, s, squared, omega);
     }
 }
 

@@ -16,40 +16,14 @@
 namespace hweno {
 
 // Workgroups per CU the register allocation must allow.  With FP32 faces
-// the staging in LDS (21.6 KB per workgroup) admits seven; stages 2 and 3
-// keep U^n and the saved derivatives in flight through the reconstruction,
-// stage 3's wave speed is a call of its own (cell_speed_wave_max), and the
-// characteristic projections need more registers.  With FP64 faces LDS
-// (37 KB) admits four and the allocation is left to the compiler.
+// the staging in LDS (21.6 KB per workgroup) admits seven; stage 3 carries
+// the FP64 wave-speed reduction and the characteristic projections need more
+// registers.  With FP64 faces LDS (37 KB) admits four and the allocation is
+// left to the compiler.
 template <int P, int mode, bool CH> constexpr int stage1d_min_blocks() {
-    return P == P_F64 ? 1 : CH ? (mode == MODE_S3 ? 4 : 5) : (mode == MODE_RHS ? 5 : 6);
-}
-
-// Stage 3 of the 1D kernel: the exact x wave speed of the cell a thread has
-// just updated (unew), reduced over the wave, with the first non-admissible
-// cell; lane 0 of every wave writes the wave's result to s_mx / s_bad.  Not
-// inlined: the FP64 division chain would otherwise raise the register
-// allocation, and with it lower the occupancy, of the whole kernel.
-template <int FLUX, int K>
-__device__ __attribute__((noinline)) void cell_speed_wave_max(bool emit, const double* unew,
-                                                              int gi, const Scheme& sch,
-                                                              double* s_mx, long long* s_bad) {
-    double mx = 0.0;
-    long long bad = LLONG_MAX;
-    if (emit) {
-        double u[K];
-#pragma unroll
-        for (int c = 0; c < K; ++c) u[c] = unew[c];
-        double sx, sy;
-        if (wave_speed<FLUX, 1, K>(u, sch, sx, sy)) mx = sx;
-        else bad = gi;
-    }
-    mx = wave_max_d(mx);
-    if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
-    if ((threadIdx.x & 63) == 0) {
-        s_mx[threadIdx.x >> 6] = mx;
-        s_bad[threadIdx.x >> 6] = bad;
-    }
+    return P == P_F64 ? 1
+                      : CH ? (mode == MODE_S3 ? 4 : 5)
+                           : (mode == MODE_S3 || mode == MODE_RHS ? 5 : 6);
 }
 
 template <int P, int K, int FLUX, int mode, bool CH>
@@ -147,7 +121,7 @@ __global__ void __launch_bounds__(256, (stage1d_min_blocks<P, mode, CH>())) stag
             beta[1] = dm * dm;
             beta[2] = dp * dp;
             T w[3];
-            nonlinear_weights<T, 2>(beta, sch, squared, w);
+            nonlinear_weights<T, 2, false>(beta, sch, squared, w);
             const T a0 = w[0] * g0inv;
             const T b1 = w[1] - a0 * (T)sch.gam[1], b2 = w[2] - a0 * (T)sch.gam[2];
             T C[5];
@@ -268,7 +242,19 @@ __global__ void __launch_bounds__(256, (stage1d_min_blocks<P, mode, CH>())) stag
             // step uses no other), for the next step: reduced over the wave
             // here and over the workgroup below; the first non-admissible
             // cell is reduced only where there is one
-            cell_speed_wave_max<FLUX, K>(emit, unew, gi, sch, s_mx, s_bad);
+            double mx = 0.0;
+            long long bad = LLONG_MAX;
+            if (emit) {
+                double sx, sy;
+                if (wave_speed<FLUX, 1, K>(unew, sch, sx, sy)) mx = sx;
+                else bad = gi;
+            }
+            mx = wave_max_d(mx);
+            if (__any(bad != LLONG_MAX)) bad = wave_min_ll(bad);
+            if ((tid & 63) == 0) {
+                s_mx[tid >> 6] = mx;
+                s_bad[tid >> 6] = bad;
+            }
         }
         __syncthreads();   // LDS reuse by the next tile
         if (mode == MODE_S3 && tid == 0) {

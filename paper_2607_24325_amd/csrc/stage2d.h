@@ -97,7 +97,7 @@ __device__ __forceinline__ void reconstruct2d(const T* q, const Scheme& s, int s
     beta[3] = sE2 + sN2;
     beta[4] = sW2 + sN2;
     T w[5];
-    nonlinear_weights<T, 4>(beta, s, squared, w);
+    nonlinear_weights<T, 4, true>(beta, s, squared, w);
     // u_ij = w0/g0 p0 + sum_m (w_m - w0 g_m/g0) p_m   (eq. hweno-reconstruction-2D)
     const T a0 = w[0] * (T)(1.0 / s.gam[0]);
     T bm[4];
