@@ -237,7 +237,10 @@ int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
 
 /* Times candidate launch configurations (segment heights, persistent grid
  * sizes, register variants; the caller's use_graph is kept) on a few steps
- * of the handle's current state, which it restores, and keeps the fastest.
+ * of the handle's current state, which it restores: after at least 50 ms of
+ * warm-up steps, every candidate on three steps, then the four fastest and
+ * the configuration in use on six steps, twice; the configuration in use is
+ * kept unless another is more than 1% faster.
  * If the environment variable HWENO_TUNING_CACHE names a file, a
  * configuration stored there for the same device, dimension, flux,
  * precision, Gauss points, reconstruction and size class (problems and

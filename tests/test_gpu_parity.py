@@ -207,6 +207,36 @@ def test_results_independent_of_tiling_and_graphs(prec):
         np.testing.assert_array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F32_KAHAN, hw.F32, hw.F64])
+def test_1d_results_and_time_steps_independent_of_launch(prec):
+    """1D: bitwise-identical states after three steps for one workgroup per
+    tile or a persistent grid, graph or eager launch (and the register
+    variant setting, which the 1D kernels ignore); every time step equals
+    the one the oracle's speeds of the state give."""
+    entries = W.batched_1d(seed=5, nprob=12, nmin=40, nmax=700)
+    specs = [e[0] for e in entries]
+    states = [W.batched_1d_state(e) for e in entries]
+    cfg = hw.default_config(1, precision=prec)
+    outs = []
+    for grid, graph, var in [(0, 1, 0), (0, 1, 1), (5, 0, 1), (3, 1, 0), (0, 0, 1)]:
+        with hw.Handle(specs, cfg) as h:
+            for i, s in enumerate(states):
+                h.set_state(i, s)
+            h.set_tuning(grid_blocks=grid, use_graph=graph, variant=var)
+            h.step()
+            for _ in range(2):
+                cur = [h.get_state(i)[0] for i in range(len(specs))]
+                dts = h.step(want_dt=True)
+                for i, sp in enumerate(specs):
+                    p = oproblem(sp, cfg)
+                    ax, ay = O.alpha(p, cur[i])
+                    assert dts[i] == O.dt(p, ax, ay, cfg.cfl), (grid, graph, var, i)
+            outs.append([h.get_state(i)[0] for i in range(len(specs))])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            np.testing.assert_array_equal(a, b)
+
+
 @pytest.mark.parametrize("prec", [hw.F32_ACC64, hw.F64, hw.F32_KAHAN])
 def test_fused_wave_speeds_equal_a_fresh_reduction(prec):
     """Stage 3 gathers the wave speeds of the state it writes (in groups of
