@@ -36,22 +36,26 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
-# the copy calibration), and VALU wave-instructions per launch, for the
-# kernel sources of this hash; any change of the sources invalidates them
-# (reported as null until measured again).
-PROFILED_SOURCES = "0b8254c236520d13"
-PROFILED_TRAFFIC = {"f32acc64": 874.3e6, "f64": 1271.4e6}
-PROFILED_VALU = {"f32acc64": 148.5e6, "f64": 168.1e6}
-# the launch configuration (tile_rows, grid_blocks) those counters were taken
-# with: the halo re-reads depend on it
-PROFILED_LAUNCH = {"f32acc64": (48, 1024), "f64": (48, 0)}
+# the copy calibration) and VALU wave-instructions per launch, per path and
+# launch configuration (tile_rows, grid_blocks: the halo re-reads depend on
+# it), for the kernel sources of this hash; any change of the sources
+# invalidates them, and a configuration not profiled has none (both are
+# reported as null).
+PROFILED_SOURCES = "00732c10b3bbf93b"
+PROFILED = {("f32acc64", 32, 0): (867.5e6, 152.0e6),
+            ("f64", 48, 0): (1271.5e6, 168.3e6),
+            ("f64", 32, 0): (1283.0e6, 171.9e6),
+            ("f32acc64_characteristic", 32, 512): (810.6e6, 357.3e6),
+            ("f32acc64_characteristic", 32, 0): (814.5e6, 357.9e6),
+            ("batched_1d", 64, 0): (1857.3e6, 147.3e6)}
 
 
 def kernel_sources_hash() -> str:
     import hashlib
     d = os.path.join(ROOT, "paper_2607_24325_amd", "csrc")
     src = "".join(open(os.path.join(d, f)).read()
-                  for f in ("stage2d.h", "device_common.h", "ff.h", "internal.h"))
+                  for f in ("stage2d.h", "stage2d_char.h", "stage1d.h", "device_common.h", "ff.h",
+                            "internal.h"))
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
@@ -191,10 +195,10 @@ def roofline(B, cells, stage_ms, key, kernel, tuning):
     """HBM roofline of the dominant kernel from its algorithmic bytes and its
     mean launch time measured with HIP events"""
     achieved = B * cells / (stage_ms * 1e-3) / 1e9
-    same = (kernel_sources_hash() == PROFILED_SOURCES and
-            PROFILED_LAUNCH.get(key) == (tuning["tile_rows"], tuning["grid_blocks"]))
-    traffic = PROFILED_TRAFFIC.get(key) if same else None
-    valu = PROFILED_VALU.get(key) if same else None
+    prof = None
+    if kernel_sources_hash() == PROFILED_SOURCES:
+        prof = PROFILED.get((key, tuning["tile_rows"], tuning["grid_blocks"]))
+    traffic, valu = prof if prof else (None, None)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "traffic_unit": "HBM bytes per stage launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
@@ -231,7 +235,9 @@ def bench_single(hw, W, O, spec, st, prec, charwise, args, dev, stream, threads,
         for name, how in runs:
             h.set_state(0, st)
             r = {}
-            if how == "autotune":
+            if how == "autotune" and args.launch:
+                h.set_tuning(**args.launch)
+            elif how == "autotune":
                 t0 = time.perf_counter()
                 tun = h.autotune()
                 r["autotune_s"] = time.perf_counter() - t0
@@ -293,11 +299,19 @@ def bench_batched(hw, W, O, dim, prec, args, dev, stream, threads, tune):
             r["errors_first_step"] = {k: max(e[k] for e in errs) for k in ("l1", "linf", "rho_l1",
                                                                             "dt_rel_diff")}
             r["errors_first_step"]["cells"] = f"all cells of the {len(small)} smallest problems"
+        if args.burn_in:
+            h.steps(args.burn_in)     # clocks up (the states are set again below)
+            torch.cuda.synchronize()
         for i, s in enumerate(states):
             h.set_state(i, s)
-        if tune:
+        if tune and args.launch:
+            h.set_tuning(**args.launch)
+            r["tuning"] = tuning_dict(h.tuning())
+        elif tune:
             tun = h.autotune()
             r["tuning"] = tuning_dict(tun)
+        else:
+            r["tuning"] = tuning_dict(h.tuning())
         ms_step, _, tm = timed_run(h, stream, args.steps, args.warmup, allow_nonfinite=True)
         stage_ms = tm.stage_ms / tm.stage_launches
         # the scheme has no positivity limiter: a problem whose state becomes
@@ -311,10 +325,15 @@ def bench_batched(hw, W, O, dim, prec, args, dev, stream, threads, tune):
         h.close()
         del ws
     B = algorithmic_bytes_per_cell_stage(K, dim, su, sd)
+    tun = r["tuning"]
+    prof = (PROFILED.get((f"batched_{dim}d", tun["tile_rows"], tun["grid_blocks"]))
+            if kernel_sources_hash() == PROFILED_SOURCES else None)
     r.update({"problems": len(specs), "cells": ncell, "value": 3.0 * live / (ms_step * 1e-3),
               "problems_frozen_nonadmissible": failed, "unit": "cell-stage updates/s",
               "ms_per_step": ms_step, "stage_kernel_ms": stage_ms, "bytes_per_cell_stage": B,
               "stage_hbm_frac": B * live / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "stage_traffic": prof[0] if prof else None,
+              "stage_valu_wave_instructions": prof[1] if prof else None,
               "conservation_drift": max(dr) if dr else None,
               "conservation_drift_problems": f"{len(dr)} problems periodic on every axis"
               if dr else "none (transmissive)",
@@ -388,6 +407,8 @@ def main():
     ap.add_argument("--burn-in", type=int, default=200,
                     help="untimed steps before a path's first measurement")
     ap.add_argument("--no-tune", action="store_true", help="library defaults only")
+    ap.add_argument("--launch", default=None,
+                    help="ROWS,GRID,VARIANT: this launch configuration instead of the tuner's")
     ap.add_argument("--precision", default="all", choices=["all", "f32acc64", "f64"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 1 GiB with a plain device copy (HBM counter scale)")
@@ -396,7 +417,12 @@ def main():
                     help="run only the batched 1D or 2D workload (profiling)")
     ap.add_argument("--profile-only", action="store_true",
                     help="only the timed steps of the 2048^2 paths (for profilers)")
+    ap.add_argument("--characteristic", action="store_true",
+                    help="with --profile-only: also the characteristic-variable path")
     args = ap.parse_args()
+    if args.launch:
+        r_, g_, v_ = (int(x) for x in args.launch.split(","))
+        args.launch = {"tile_rows": r_, "grid_blocks": g_, "variant": v_}
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
@@ -427,7 +453,7 @@ def main():
 
     if args.only_batched:
         prec = hw.F32_ACC64 if args.only_batched == 1 else hw.F32_KAHAN
-        r = bench_batched(hw, W, None, args.only_batched, prec, args, dev, stream, ncores, False)
+        r = bench_batched(hw, W, None, args.only_batched, prec, args, dev, stream, ncores, tune)
         print(json.dumps({f"batched_{args.only_batched}d": r}))
         return
     if args.copy_calibration:
@@ -456,7 +482,7 @@ def main():
     runs = [("f32acc64", hw.F32_ACC64, 0), ("f64", hw.F64, 0)]
     if args.precision != "all":
         runs = [r for r in runs if r[0] == args.precision]
-    elif not args.profile_only:
+    elif not args.profile_only or args.characteristic:
         runs.append(("f32acc64_characteristic", hw.F32_ACC64, 1))
     results = {}
     for name, prec, charwise in runs:
@@ -504,8 +530,8 @@ def main():
 
     main_r = path(results["f32acc64"], "f32acc64", "stage2d_kernel (F32_ACC64)", 8, 4)
     f64_r = path(results["f64"], "f64", "stage2d_kernel (F64)", 8, 8)
-    ch = results["f32acc64_characteristic"]
-    ch_best = ch.get("tuned", ch["default"])
+    ch_r = path(results["f32acc64_characteristic"], "f32acc64_characteristic",
+                "stage2d_char_kernel (F32_ACC64)", 8, 4)
     line = {
         "metric": "cell-stage updates/s (2D Euler 2048^2, FP32 vs FP64) + % HBM peak + L1 err",
         "value": main_r["value"],
@@ -528,11 +554,7 @@ def main():
         "conservation_drift": main_r["conservation_drift"],
         "default_launch": main_r["default_launch"],
         "fp64_path": f64_r,
-        "characteristic_path": {"value": ch_best["value"], "ms_per_step": ch_best["ms_per_step"],
-                                "stage_kernel_ms": ch_best["stage_kernel_ms"],
-                                "tuning": ch_best["tuning"],
-                                "errors_first_step": ch.get("errors_first_step"),
-                                "conservation_drift": ch_best["conservation_drift"]},
+        "characteristic_path": ch_r,
         "stage_kernel_ms": main_r["stage_kernel_ms"],
         "cpu_baseline": cpu,
     }
