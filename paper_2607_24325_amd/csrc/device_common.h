@@ -175,22 +175,32 @@ template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
             out[3] = H * dn + v * (dE + dp) - v * H * dr;
         }
     }
-    __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
-                                         T* fw) const {
+    // velocity, half its square, pressure and total enthalpy of U
+    struct Prim {
+        T u, v, q2h, p, H;
+    };
+    __device__ __forceinline__ Prim prim(const T* U) const {
         const T rho = U[0], m = U[1], n = U[2], E = U[3];
         const T ir = rcp(rho);
         const T u = m * ir, v = n * ir;
         const T q2h = (T)0.5 * (u * u + v * v);
         const T p = gm1 * (E - rho * q2h);
-        const T Ep = E + p;
-        const T H = Ep * ir;
+        return {u, v, q2h, p, (E + p) * ir};
+    }
+    __device__ __forceinline__ void flux(const T* U, const Prim& w, T* f) const {
+        const T m = U[1], n = U[2], Ep = U[3] + w.p;
         if (DIR == 0) {
-            f[0] = m; f[1] = m * u + p; f[2] = m * v; f[3] = u * Ep;
+            f[0] = m; f[1] = m * w.u + w.p; f[2] = m * w.v; f[3] = w.u * Ep;
         } else {
-            f[0] = n; f[1] = n * u; f[2] = n * v + p; f[3] = v * Ep;
+            f[0] = n; f[1] = n * w.u; f[2] = n * w.v + w.p; f[3] = w.v * Ep;
         }
-        jvp(u, v, q2h, H, V, fv);
-        jvp(u, v, q2h, H, W, fw);
+    }
+    __device__ __forceinline__ void side(const T* U, const T* V, const T* W, T* f, T* fv,
+                                         T* fw) const {
+        const Prim w = prim(U);
+        flux(U, w, f);
+        jvp(w.u, w.v, w.q2h, w.H, V, fv);
+        jvp(w.u, w.v, w.q2h, w.H, W, fw);
     }
 };
 

@@ -191,7 +191,9 @@ __device__ __forceinline__ void lf_edge(const Flux<T, FLUX, K, DIR>& F, const T*
 // Variant 0: the occupancy the face arrays and registers comfortably allow
 // (every stage fits four FP32-face workgroups in 128 registers, the edge
 // flux accumulating one side at a time and stage 3's speed gather being a
-// call of its own after the march); variant 1: one workgroup more per CU,
+// call of its own after the march; with FP64 faces the streamed edge flux
+// keeps every stage within the 168 registers of three workgroups, which
+// their 48 KB of LDS also allow); variant 1: one workgroup more per CU,
 // which caps the registers lower (the compiler may spill).  The tuner picks.
 template <int P, int Q, int mode, int V> constexpr int stage2d_min_blocks() {
     return V + (P == P_F64 ? (Q == 3 ? 1 : 2) : (Q == 3 ? 2 : 4));
@@ -294,7 +296,13 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
         T ytop[Q][3];            // top-face values of the previous row (this lane, comp)
         // previous row's flux sums: x differences and y sums of the
         // cell-average fluxes in the accumulation type, of the derivative
-        // fluxes in T
+        // fluxes in T.  The FP64 path (PARTIAL) carries instead the part of
+        // the previous row's residual known before its top edge (its x
+        // difference less its bottom edge, in xdu_prev and xdd_prev): three
+        // register pairs fewer through the march.  (In single precision
+        // that form would round the sum of two large terms instead of their
+        // small difference.)
+        constexpr bool PARTIAL = P == P_F64;
         TA xdu_prev = 0, gyu_prev = 0;
         T xdd_prev[2] = {0, 0}, gyd_prev[2] = {0, 0};
         T hat_prev[2] = {0, 0};
@@ -403,6 +411,51 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
                     const int kind = sl / (Q * 64);
                     const int mu = (sl >> 6) % Q;
                     const int l = sl & 63;
+                    if constexpr (P == P_F64 && FLUX == F_EULER && K == 4) {
+                        // one side at a time, and within a side the flux and
+                        // its two Jacobian-vector products one after the
+                        // other, each from its own four face values: fewer
+                        // registers at the register peak of the FP64 march
+                        T out[3 * K];
+                        auto side = [&](auto& F, T (*src)[64], int ll, T al, bool first) {
+                            const int b = mu * 3 * K;
+                            T U[K], D[K], o[K];
+#pragma unroll
+                            for (int k = 0; k < K; ++k) U[k] = src[b + k][ll];
+                            const auto w = F.prim(U);
+                            F.flux(U, w, o);
+#pragma unroll
+                            for (int k = 0; k < K; ++k) {
+                                const T ok = o[k] + al * U[k];
+                                out[k] = first ? ok : out[k] + ok;
+                            }
+#pragma unroll
+                            for (int sk = 1; sk < 3; ++sk) {
+#pragma unroll
+                                for (int k = 0; k < K; ++k) D[k] = src[b + sk * K + k][ll];
+                                F.jvp(w.u, w.v, w.q2h, w.H, D, o);
+#pragma unroll
+                                for (int k = 0; k < K; ++k) {
+                                    const T ok = o[k] + al * D[k];
+                                    out[sk * K + k] = first ? ok : out[sk * K + k] + ok;
+                                }
+                            }
+                        };
+                        if (kind == 0) {
+                            if (l < 63) {   // x-edge between lanes l and l+1
+                                side(FXf, sxR, l, ax, true);
+                                side(FXf, sxL, l + 1, -ax, false);
+#pragma unroll
+                                for (int k = 0; k < 3 * K; ++k) FX(mu, k, l) = out[k];
+                            }
+                        } else {            // y-edge between rows r-1 and r, column l
+                            side(FYf, syT, l, ay, true);
+                            side(FYf, syB, l, -ay, false);
+#pragma unroll
+                            for (int k = 0; k < 3 * K; ++k) FY(mu, k, l) = out[k];
+                        }
+                        continue;
+                    }
                     T UL[K], VL[K], WL[K], UR[K], VR[K], WR[K], out[3 * K];
                     if (kind == 0) {
                         if (l < 63) {   // x-edge between lanes l and l+1
@@ -447,9 +500,14 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
                     for (int mu = 0; mu < Q; ++mu) {
                         const T w = (T)(0.5 * Gauss<Q>::w(mu));   // fluxes are stored doubled
                         fr += w * FX(mu, sk * K + c, lane);
-                        fl += w * FX(mu, sk * K + c, lane > 0 ? lane - 1 : 0);
+                        if constexpr (P != P_F64)
+                            fl += w * FX(mu, sk * K + c, lane > 0 ? lane - 1 : 0);
                         g += w * FY(mu, sk * K + c, lane);
                     }
+                    // FP64: the left edge's sum is the left lane's right-edge
+                    // sum, the same bits, taken by a lane shift instead of
+                    // further LDS reads (the FP64 march is LDS-heavy)
+                    if constexpr (P == P_F64) fl = from_left(fr);
                     if (sk == 0) {
                         xdu = (TA)fr - (TA)fl;
                         gyu = (TA)g;
@@ -459,10 +517,18 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
                     }
                 }
                 if (r > j0) {
-                    const TA Lu = -(xdu_prev * inv_dx_a + (gyu - gyu_prev) * inv_dy_a);
                     // v- and w-fluxes carry the derivatives in local units
-                    const T Lv = -inv_dx * (xdd_prev[0] + rx * (gyd[0] - gyd_prev[0]));
-                    const T Lw = -inv_dy * (ry * xdd_prev[1] + (gyd[1] - gyd_prev[1]));
+                    TA Lu;
+                    T Lv, Lw;
+                    if constexpr (PARTIAL) {
+                        Lu = -(xdu_prev + gyu * inv_dy_a);
+                        Lv = -inv_dx * (xdd_prev[0] + rx * gyd[0]);
+                        Lw = -inv_dy * (xdd_prev[1] + gyd[1]);
+                    } else {
+                        Lu = -(xdu_prev * inv_dx_a + (gyu - gyu_prev) * inv_dy_a);
+                        Lv = -inv_dx * (xdd_prev[0] + rx * (gyd[0] - gyd_prev[0]));
+                        Lw = -inv_dy * (ry * xdd_prev[1] + (gyd[1] - gyd_prev[1]));
+                    }
                     if (emit) {
                         const TA ucur = (TA)um;   // u-bar of row r-1 in the input set
                         if (mode == MODE_RHS) {
@@ -497,12 +563,18 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
                         }
                     }
                 }
-                xdu_prev = xdu;
-                gyu_prev = gyu;
+                if constexpr (PARTIAL) {
+                    xdu_prev = xdu * inv_dx_a - gyu * inv_dy_a;
+                    xdd_prev[0] = xdd[0] - rx * gyd[0];
+                    xdd_prev[1] = ry * xdd[1] - gyd[1];
+                } else {
+                    xdu_prev = xdu;
+                    gyu_prev = gyu;
 #pragma unroll
-                for (int sk = 0; sk < 2; ++sk) {
-                    xdd_prev[sk] = xdd[sk];
-                    gyd_prev[sk] = gyd[sk];
+                    for (int sk = 0; sk < 2; ++sk) {
+                        xdd_prev[sk] = xdd[sk];
+                        gyd_prev[sk] = gyd[sk];
+                    }
                 }
             }
             hat_prev[0] = vhat;
