@@ -3,8 +3,11 @@
 all six meshes, against the printed HWENO rows.  L1 = mean over cells of the
 cell-average error against exact cell averages (density for Euler), L-inf =
 its maximum.  The GPU errors sit at 0.95x the printed ones from N = 80 on
-(the oracle shows the same uniform offset); the bars are those of the
-oracle's own table pins."""
+(the oracle shows the same uniform offset, which the Lax-Friedrichs
+dissipation explains).  Coarse meshes: within 10-15% of the printed values;
+from N = 120 on: inside the narrow band of that offset (0.93-0.975; Table 2's
+L1 0.95-0.975, its L-inf 0.9-0.95 from N = 160), so that a change of a few
+percent in the scheme's error fails."""
 import numpy as np
 import pytest
 
@@ -49,7 +52,8 @@ def test_table1_burgers_1d():
         res[n] = (e.mean(), e.max())
     for n in (80, 120, 160, 200, 240):
         for k in (0, 1):
-            assert 0.85 < res[n][k] / TABLE1[n][k] < 1.1, (n, k, res[n][k], TABLE1[n][k])
+            lo, hi = (0.85, 1.1) if n < 120 else (0.93, 0.975)
+            assert lo < res[n][k] / TABLE1[n][k] < hi, (n, k, res[n][k], TABLE1[n][k])
     ours, paper = _orders(res), _orders(TABLE1)
     for ab in ours:
         if ab[0] >= 80:
@@ -57,17 +61,19 @@ def test_table1_burgers_1d():
 
 
 def test_table2_euler_1d():
-    """density L1 within 10% on every mesh; L-inf within 15% from N = 160 on
-    (on coarse meshes the printed L-inf errors are larger than ours)"""
+    """density L1 within 10% on the coarse meshes and at 0.95-0.975 of the
+    printed values from N = 120 on; L-inf at 0.9-0.95 from N = 160 on (on
+    coarse meshes the printed L-inf errors are larger than ours)"""
     for n, (l1, li) in TABLE2.items():
         spec, st = W.euler_1d_smooth(n)
         dx = spec.dx
         xl = dx * np.arange(n)
         ex = 1 + 0.2 * (np.cos(np.pi * (xl - 2)) - np.cos(np.pi * (xl + dx - 2))) / (np.pi * dx)
         e = np.abs(_run(spec, st)[0, 0, 0] - ex)
-        assert 0.9 < e.mean() / l1 < 1.1, (n, e.mean(), l1)
+        lo, hi = (0.9, 1.1) if n < 120 else (0.95, 0.975)
+        assert lo < e.mean() / l1 < hi, (n, e.mean(), l1)
         if n >= 160:
-            assert 0.85 < e.max() / li < 1.1, (n, e.max(), li)
+            assert 0.9 < e.max() / li < 0.95, (n, e.max(), li)
 
 
 def test_table3_burgers_2d():
@@ -76,8 +82,9 @@ def test_table3_burgers_2d():
         spec, st = W.burgers_2d(n)
         e = np.abs(_run(spec, st)[0, 0] - burgers2d_exact_avg(n, spec.t_end))
         res[n] = (e.mean(), e.max())
+        lo, hi = (0.9, 1.1) if n < 120 else (0.93, 0.975)
         for k in (0, 1):
-            assert 0.9 < res[n][k] / TABLE3[n][k] < 1.1, (n, k, res[n][k], TABLE3[n][k])
+            assert lo < res[n][k] / TABLE3[n][k] < hi, (n, k, res[n][k], TABLE3[n][k])
 
 
 def _euler2d_exact_avg(n, t, nq=6):
@@ -94,15 +101,16 @@ def _euler2d_exact_avg(n, t, nq=6):
 
 
 def test_table4_euler_2d():
-    """Example 4: density errors within 10% of the printed ones on all six
-    meshes, orders within 0.1"""
+    """Example 4: density errors within 10% of the printed ones on the coarse
+    meshes and at 0.93-0.975 of them from N = 120 on, orders within 0.1"""
     res = {}
     for n in TABLE4:
         spec, st = W.euler_2d_smooth(n)
         e = np.abs(_run(spec, st)[0, 0] - _euler2d_exact_avg(n, spec.t_end))
         res[n] = (e.mean(), e.max())
+        lo, hi = (0.9, 1.1) if n < 120 else (0.93, 0.975)
         for k in (0, 1):
-            assert 0.9 < res[n][k] / TABLE4[n][k] < 1.1, (n, k, res[n][k], TABLE4[n][k])
+            assert lo < res[n][k] / TABLE4[n][k] < hi, (n, k, res[n][k], TABLE4[n][k])
     ours, paper = _orders(res), _orders(TABLE4)
     for ab in ours:
         assert abs(ours[ab] - paper[ab]) < 0.1, (ab, ours[ab], paper[ab])

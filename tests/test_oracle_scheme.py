@@ -242,7 +242,10 @@ TABLE1 = {40: (2.66e-05, 1.39e-04), 80: (3.65e-07, 4.32e-06), 120: (4.64e-08, 6.
 def test_table1_burgers_1d():
     """Example 1 / Table 1 (HWENO rows): with L1 = mean over cells of the
     cell-average error and dt = 0.6 dx^(5/3) / alpha, the oracle reproduces
-    the printed errors within 15% for N >= 80 and the orders within 0.2."""
+    the printed errors within 15% for N >= 80 and the orders within 0.2;
+    from N = 120 on both norms sit at 0.93-0.975 of the printed values (the
+    uniform offset that the Lax-Friedrichs dissipation explains: a change of
+    a few percent in the scheme's error moves them out)."""
     res = {}
     for n in TABLE1:
         spec, st = W.burgers_1d(n)
@@ -252,7 +255,8 @@ def test_table1_burgers_1d():
         res[n] = (e.mean(), e.max())
     for n in (80, 120, 160, 200, 240):
         for k in (0, 1):
-            assert 0.85 < res[n][k] / TABLE1[n][k] < 1.1, (n, k, res[n][k], TABLE1[n][k])
+            lo, hi = (0.85, 1.1) if n < 120 else (0.93, 0.975)
+            assert lo < res[n][k] / TABLE1[n][k] < hi, (n, k, res[n][k], TABLE1[n][k])
     ns = sorted(TABLE1)
     for a, b in zip(ns[1:], ns[2:]):
         ours = np.log(res[a][0] / res[b][0]) / np.log(b / a)
