@@ -243,10 +243,28 @@ __device__ __forceinline__ bool wave_speed(const double* u, const Scheme& sch, d
     return ok;
 }
 
+// Maximum over the wave of a non-negative double, returned to every lane:
+// DPP steps within quads, half rows and rows, then the row broadcasts of the
+// GFX9 data-parallel primitives (row_bcast:15 into rows 1 and 3, then
+// row_bcast:31 into rows 2 and 3) leave it in lane 63, which is read out.
+// Lanes a broadcast does not write see 0, which leaves a non-negative
+// maximum as it is.  (An xor butterfly through ds_bpermute costs LDS round
+// trips and more instructions.)
+template <int CTRL, int ROWS> __device__ __forceinline__ double dpp_or_zero(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xF, ROWS == 0xF),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xF, ROWS == 0xF));
+}
+__device__ __forceinline__ double max_of(double a, double b) { return b > a ? b : a; }
 __device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = max_of(v, dpp_or_zero<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+    v = max_of(v, dpp_or_zero<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+    v = max_of(v, dpp_or_zero<0x141, 0xF>(v));   // row_half_mirror
+    v = max_of(v, dpp_or_zero<0x140, 0xF>(v));   // row_mirror
+    v = max_of(v, dpp_or_zero<0x142, 0xA>(v));   // row_bcast:15
+    v = max_of(v, dpp_or_zero<0x143, 0xC>(v));   // row_bcast:31
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 __device__ __forceinline__ long long wave_min_ll(long long v) {
