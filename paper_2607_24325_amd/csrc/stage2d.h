@@ -293,6 +293,9 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
         load_row(j0 - 2, um, vm, wm);
         load_row(j0 - 1, u0, v0, w0);
         load_row(j0, up, vp, wp);
+        constexpr bool SYMD = sizeof(T) == 4 && (std::is_same<TU, double>::value || std::is_same<TU, float>::value);
+        T dneg = 0;
+        if constexpr (SYMD) dneg = (T)(u0 - um);
         T ytop[Q][3];            // top-face values of the previous row (this lane, comp)
         // previous row's flux sums: x differences and y sums of the
         // cell-average fluxes in the accumulation type, of the derivative
@@ -339,8 +342,16 @@ __global__ void __launch_bounds__(64 * K, (stage2d_min_blocks<P, Q, mode, V>()))
                 // centre difference, which the compiler forms in one add with a
                 // DPP lane shift on its first operand.
                 const TU uc = u0;
-                const T dm = (T)(um - uc), dp = (T)(up - uc);
-                const T dl = (T)(from_left(u0) - uc), dr = (T)(from_right(u0) - uc);
+                const T dp = (T)(up - uc), dr = (T)(from_right(u0) - uc);
+                T dm, dl;
+                if constexpr (SYMD) {
+                    dm = -dneg;
+                    dl = -from_left(dr);
+                    dneg = dp;
+                } else {
+                    dm = (T)(um - uc);
+                    dl = (T)(from_left(u0) - uc);
+                }
                 q[0] = from_left(dm) + dl;
                 q[1] = dm;
                 q[2] = from_right(dm) + dr;
