@@ -37,17 +37,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per stage launch measured with FETCH_SIZE / WRITE_SIZE (scaled by
 # the copy calibration) and VALU wave-instructions per launch, per path and
-# launch configuration (tile_rows, grid_blocks: the halo re-reads depend on
-# it), for the kernel sources of this hash; any change of the sources
+# launch configuration (tile_rows, grid_blocks, variant: the halo re-reads
+# depend on the first two, the instruction count on the last), for the
+# kernel sources of this hash; any change of the sources
 # invalidates them, and a configuration not profiled has none (both are
 # reported as null).
 PROFILED_SOURCES = "d3a320806643a959"
-PROFILED = {("f32acc64", 32, 0): (867.1e6, 152.0e6),
-            ("f64", 48, 0): (1276.5e6, 168.3e6),
-            ("f64", 32, 0): (1293.8e6, 172.3e6),
-            ("f32acc64_characteristic", 32, 512): (810.6e6, 357.3e6),
-            ("f32acc64_characteristic", 32, 0): (814.5e6, 357.9e6),
-            ("batched_1d", 64, 0): (1857.3e6, 147.3e6)}
+PROFILED = {("f32acc64", 32, 0, 0): (867.1e6, 152.0e6),
+            ("f64", 48, 0, 1): (1276.5e6, 168.3e6),
+            ("f32acc64_characteristic", 32, 512, 0): (810.6e6, 357.3e6),
+            ("batched_1d", 64, 0, 0): (1857.3e6, 147.3e6)}
 
 
 def kernel_sources_hash() -> str:
@@ -197,7 +196,7 @@ def roofline(B, cells, stage_ms, key, kernel, tuning):
     achieved = B * cells / (stage_ms * 1e-3) / 1e9
     prof = None
     if kernel_sources_hash() == PROFILED_SOURCES:
-        prof = PROFILED.get((key, tuning["tile_rows"], tuning["grid_blocks"]))
+        prof = PROFILED.get((key, tuning["tile_rows"], tuning["grid_blocks"], tuning["variant"]))
     traffic, valu = prof if prof else (None, None)
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -326,7 +325,7 @@ def bench_batched(hw, W, O, dim, prec, args, dev, stream, threads, tune):
         del ws
     B = algorithmic_bytes_per_cell_stage(K, dim, su, sd)
     tun = r["tuning"]
-    prof = (PROFILED.get((f"batched_{dim}d", tun["tile_rows"], tun["grid_blocks"]))
+    prof = (PROFILED.get((f"batched_{dim}d", tun["tile_rows"], tun["grid_blocks"], tun["variant"]))
             if kernel_sources_hash() == PROFILED_SOURCES else None)
     r.update({"problems": len(specs), "cells": ncell, "value": 3.0 * live / (ms_step * 1e-3),
               "problems_frozen_nonadmissible": failed, "unit": "cell-stage updates/s",

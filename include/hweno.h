@@ -235,8 +235,10 @@ int hweno_get_tuning(const hweno_handle* h, hweno_tuning* t);
 /* Errors: ERR_ARG for values out of range. */
 int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
 
-/* Times candidate launch configurations (segment heights, persistent grid
- * sizes, register variants; the caller's use_graph is kept) on a few steps
+/* Times candidate launch configurations (segment heights 16-64 and those
+ * whose tile count just fits two or three rounds of the GPU's workgroup
+ * slots, persistent grid sizes, register variants; the caller's use_graph
+ * is kept) on a few steps
  * of the handle's current state, which it restores: after at least 50 ms of
  * warm-up steps, every candidate on three steps, then the four fastest and
  * the configuration in use on six steps, twice; the configuration in use is

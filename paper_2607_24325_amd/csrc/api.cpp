@@ -899,6 +899,30 @@ static std::vector<hweno_tuning> tuning_candidates(hweno_handle* h) {
     for (int v = 0; v < nvar; ++v)
         for (int rows : {16, 24, 32, 48, 64})
             for (int g : {0, 2 * ncu, 3 * ncu, 4 * ncu}) cands.push_back({rows, g, graph, v, 0, 0});
+    // With one workgroup per tile, a tile count just above a whole number of
+    // rounds of the GPU's workgroup slots leaves a last round that runs the
+    // chip mostly idle.  Also try the lowest segment heights whose tile count
+    // fits 2 or 3 rounds at 3 or 4 resident workgroups per CU (the Euler
+    // kernels' occupancy in double and single precision).
+    auto ntiles = [&](int rows) {
+        long long n = 0;
+        for (const hweno_problem& p : h->probs)
+            n += (long long)((p.nx + STRIP_OUT - 1) / STRIP_OUT) * ((p.ny + rows - 1) / rows);
+        return n;
+    };
+    std::vector<int> fit;
+    for (int per_cu : {3, 4})
+        for (int rounds : {2, 3}) {
+            const long long slots = (long long)rounds * per_cu * ncu;
+            for (int rows = 16; rows <= 64; ++rows)
+                if (ntiles(rows) <= slots) {
+                    if (rows % 8 != 0 && std::find(fit.begin(), fit.end(), rows) == fit.end())
+                        fit.push_back(rows);
+                    break;
+                }
+        }
+    for (int v = 0; v < nvar; ++v)
+        for (int rows : fit) cands.push_back({rows, 0, graph, v, 0, 0});
     return cands;
 }
 
