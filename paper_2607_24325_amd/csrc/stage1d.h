@@ -16,14 +16,24 @@
 namespace hweno {
 
 // Workgroups per CU the register allocation must allow.  With FP32 faces
-// the staging in LDS (21.6 KB per workgroup) admits seven; stage 3 carries
-// the FP64 wave-speed reduction and the characteristic projections need more
-// registers.  With FP64 faces LDS (37 KB) admits four and the allocation is
-// left to the compiler.
+// the staging in LDS (21.6 KB per workgroup) admits seven; six fit the
+// registers of stages 1-3 (stage 3, with the FP64 wave-speed reduction,
+// only because it loads its RK inputs late, see stage1d_late_rk); the
+// right-hand side and the characteristic projections need more.  With FP64
+// faces LDS (37 KB) admits four and the allocation is left to the compiler.
 template <int P, int mode, bool CH> constexpr int stage1d_min_blocks() {
     return P == P_F64 ? 1
                       : CH ? (mode == MODE_S3 ? 4 : 5)
-                           : (mode == MODE_S3 || mode == MODE_RHS ? 5 : 6);
+                           : (mode == MODE_RHS ? 5 : 6);
+}
+
+// Stage 3 of the Euler system in single precision (component-wise) loads
+// U^n and the saved derivatives after the reconstruction instead of before
+// it: the nine registers they would hold through it are what separates its
+// 95 VGPRs (five workgroups per CU) from 80 (six), and the extra workgroup
+// hides more latency than the late loads expose.
+template <int P, int K, int mode, bool CH> constexpr bool stage1d_late_rk() {
+    return mode == MODE_S3 && P != P_F64 && !CH && K > 1;
 }
 
 template <int P, int K, int FLUX, int mode, bool CH>
@@ -83,21 +93,24 @@ __global__ void __launch_bounds__(256, (stage1d_min_blocks<P, mode, CH>())) stag
                 sv[c][k] = neg_if(((const TD*)a.in.d)[off_d + (int64_t)c * nx + src], mir && c != 1);
             }
         }
-        // stages 2 and 3: U^n and the saved derivatives of the output cell,
-        // loaded now (lanes without output read element 0) so that they arrive
-        // while the cell is reconstructed and the fluxes are formed
+        // stages 2 and 3: U^n and the saved derivatives of the output cell
+        // (lanes without output read element 0), loaded now so that they
+        // arrive while the cell is reconstructed and the fluxes are formed,
+        // or after the reconstruction (stage1d_late_rk)
         const int gi = c0 - 1 + tid;
         const bool emit = tid >= 1 && tid <= TILE1D_OUT && gi < nx;
+        constexpr bool LATE_RK = stage1d_late_rk<P, K, mode, CH>();
         TA unr[K];
         T hnr[K];
-        if (mode == MODE_S2 || mode == MODE_S3) {
+        auto load_rk = [&]() {
             const int gl = emit ? gi : 0;
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 unr[c] = (TA)((const TU*)a.un)[off_u + (int64_t)c * nx + gl];
                 hnr[c] = (T)((const TD*)a.h)[off_d + (int64_t)c * nx + gl];
             }
-        }
+        };
+        if constexpr ((mode == MODE_S2 || mode == MODE_S3) && !LATE_RK) load_rk();
         __syncthreads();
 
         // ---- reconstruct local cell tid (global c0 - 1 + tid) ---------------
@@ -176,6 +189,7 @@ __global__ void __launch_bounds__(256, (stage1d_min_blocks<P, mode, CH>())) stag
             sL[K + c][tid] = (De[c] - Do[c]) * inv_dx;
             vhat[c] = (T)2 * O[c] * inv_dx;   // (u(x+1/2) - u(x-1/2)) / dx
         }
+        if constexpr (LATE_RK) load_rk();
         __syncthreads();
 
         // ---- flux at the interface between local cells tid and tid+1 -------
