@@ -315,29 +315,40 @@ def test_nonadmissible_state_is_reported():
 def test_nonadmissible_state_reached_by_the_scheme_matches_oracle():
     """Problem 1390 of the seeded 4096-problem 1D batch (four Riemann states)
     develops a non-admissible state after 74 steps (the scheme has no
-    positivity limiter): the GPU reports the same step, time and cell as the
-    oracle, and keeps the state of the last admissible step."""
+    positivity limiter): the GPU reports the same step and cell as the
+    oracle, and the same time to within the problem's conditioning.  On the
+    way to vacuum the sound speed comes from the cancellation in
+    p = (gamma - 1)(E - rho |u|^2 / 2), so the time steps are ill-conditioned:
+    a relative change of 1e-15 in the initial state moves the oracle's own
+    time of failure by about 1.2e-12 relative.  The bar is the larger of
+    1e-12 and 10x that change (the rule of the final-time tests)."""
     entries = W.batched_1d(seed=1, nprob=4096)
     spec, st = entries[1390][0], W.batched_1d_state(entries[1390])
     cfg = hw.default_config(1, precision=hw.F64)
     p = oproblem(spec, cfg)
-    cur, t, n = st, 0.0, 0
-    while True:
-        try:
-            ax, _ = O.alpha(p, cur)
-        except O.OracleError as e:
-            bad_msg = str(e)
-            break
-        dt = O.dt(p, ax, 0.0, cfg.cfl)
-        cur = O.step(p, cur, ax, 0.0, dt)
-        t += dt
-        n += 1
-    cell = int(bad_msg.split()[-1])
+
+    def oracle_failure(state):
+        cur, t, n = state, 0.0, 0
+        while True:
+            try:
+                ax, _ = O.alpha(p, cur)
+            except O.OracleError as e:
+                return t, n, int(str(e).split()[-1])
+            dt = O.dt(p, ax, 0.0, cfg.cfl)
+            cur = O.step(p, cur, ax, 0.0, dt)
+            t += dt
+            n += 1
+
+    t, n, cell = oracle_failure(st)
+    own = max(abs(oracle_failure(st * (1.0 + e))[0] - t) for e in (1e-15, -1e-15))
+    tol = max(1e-12 * t, 10.0 * own)
     with _one(spec, st, cfg) as h:
         with pytest.raises(hw.HwenoError) as ei:
             h.run_to_time()
         assert ei.value.code == hw.ERR_NONFINITE
         assert f"i={cell} " in str(ei.value)
         t_gpu = float(str(ei.value).split("t=")[-1])
-        assert abs(t_gpu - t) <= 1e-12 * t
+        print(f"t {t_gpu!r} (oracle {t!r}, relative {abs(t_gpu - t) / t:.3e}; "
+              f"oracle's own change {own / t:.3e})")
+        assert abs(t_gpu - t) <= tol
         assert n == 74
