@@ -250,6 +250,15 @@ int hweno_set_tuning(hweno_handle* h, const hweno_tuning* t);
  * timed winner is appended (one JSON object per line).  Synchronising.
  * best (may be NULL) receives the configuration in use afterwards. */
 int hweno_autotune(hweno_handle* h, hweno_tuning* best);
+int hweno_autotune(hweno_handle* h, hweno_tuning* best);
+
+/* The candidate launch configurations hweno_autotune times for this handle
+ * (its problems, flux, precision and device), in the order it times them,
+ * with the handle's use_graph.  *count receives their number; the first
+ * min(count, cap) are written to out (out may be NULL when cap is 0).
+ * Errors: ERR_ARG for a NULL handle or count, cap < 0, or out NULL with
+ * cap > 0. */
+int hweno_tuning_candidates(hweno_handle* h, hweno_tuning* out, int32_t cap, int32_t* count);
 
 /* Per-kernel timing of nsteps steps (CFL rule), launched eagerly on the
  * handle's stream with a HIP event pair around every kernel.  Synchronising.

@@ -926,6 +926,17 @@ static std::vector<hweno_tuning> tuning_candidates(hweno_handle* h) {
     return cands;
 }
 
+// The candidate list hweno_autotune times, for callers that time or profile
+// the candidates themselves.
+extern "C" int hweno_tuning_candidates(hweno_handle* h, hweno_tuning* out, int32_t cap,
+                                       int32_t* count) {
+    if (!h || !count || cap < 0 || (cap > 0 && !out)) return HWENO_ERR_ARG;
+    const std::vector<hweno_tuning> c = tuning_candidates(h);
+    *count = (int32_t)c.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)c.size(); ++i) out[i] = c[i];
+    return HWENO_OK;
+}
+
 // Times a few steps per candidate launch configuration from the same saved
 // state and keeps the fastest; the state, times and counters are restored
 // afterwards.  With HWENO_TUNING_CACHE naming a file, a configuration stored

@@ -64,6 +64,7 @@ _lib = None
 EXPORTS = ["hweno_default_config", "hweno_workspace_bytes", "hweno_create", "hweno_set_state",
            "hweno_get_state", "hweno_rhs", "hweno_alpha", "hweno_step", "hweno_steps", "hweno_run_to_time",
            "hweno_sync", "hweno_get_tuning", "hweno_set_tuning", "hweno_autotune",
+           "hweno_tuning_candidates",
            "hweno_timed_steps", "hweno_step_noalloc", "hweno_destroy", "hweno_last_error"]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.hweno_get_tuning.argtypes = [H, P(hweno_tuning)]
         L.hweno_set_tuning.argtypes = [H, P(hweno_tuning)]
         L.hweno_autotune.argtypes = [H, P(hweno_tuning)]
+        L.hweno_tuning_candidates.argtypes = [H, P(hweno_tuning), C.c_int32, P(C.c_int32)]
         L.hweno_timed_steps.argtypes = [H, C.c_int32, P(hweno_timing)]
         L.hweno_step_noalloc.argtypes = [P(hweno_problem), P(hweno_config), C.c_void_p,
                                          C.c_void_p, C.c_double, C.c_double, C.c_void_p,
@@ -256,6 +258,14 @@ class Handle:
         t = hweno_tuning()
         self._check(lib().hweno_autotune(self.h, C.byref(t)))
         return t
+
+    def tuning_candidates(self):
+        """The launch configurations autotune() times, in its order."""
+        n = C.c_int32()
+        self._check(lib().hweno_tuning_candidates(self.h, None, 0, C.byref(n)))
+        out = (hweno_tuning * n.value)()
+        self._check(lib().hweno_tuning_candidates(self.h, out, n.value, C.byref(n)))
+        return list(out)
 
     def tuned_from_cache(self) -> bool:
         return self.tuning().source == TUNED_FROM_CACHE

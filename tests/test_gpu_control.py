@@ -89,7 +89,8 @@ def test_autotune_restores_state_and_speeds(steps_before):
 
 
 def test_autotune_cache_and_eager_mode(tmp_path, monkeypatch):
-    """The tuner keeps the caller's eager mode in every candidate, stores its
+    """The tuner keeps the caller's eager mode in every candidate (and picks
+    one of the configurations hweno_tuning_candidates lists), stores its
     winner in the cache file named by HWENO_TUNING_CACHE, and a second
     handle of the same class takes the stored configuration without timing;
     the tuned and cached runs give the bits of the default run."""
@@ -112,6 +113,10 @@ def test_autotune_cache_and_eager_mode(tmp_path, monkeypatch):
             outs.append(h.get_state(0)[0])
             if mode == "timed":
                 timed = (t.tile_rows, t.grid_blocks, t.variant)
+                # the winner is one of the listed candidates, all eager
+                cands = h.tuning_candidates()
+                assert timed in {(c.tile_rows, c.grid_blocks, c.variant) for c in cands}
+                assert all(c.use_graph == 0 for c in cands)
             elif mode == "cached":
                 assert (t.tile_rows, t.grid_blocks, t.variant) == timed
     lines = cache.read_text().splitlines()
