@@ -45,118 +45,158 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 PROFILED_SOURCES = "4a94129bb35d6191"
 # path, tile_rows, grid_blocks, variant: HBM MB and VALU wave-instructions (M)
 # per stage launch, mean of the three stages, for every launch configuration
-# the tuner can choose (one eager step each, 2048^2 workload; batched 1D:
-# segment heights do not apply)
+# the tuner can choose (one eager step each; 2048^2 workload, 4096-problem 1D
+# batch, where segment heights do not apply, 256-problem 2D batch)
 _PROFILED_TABLE = """
-f32acc64 16 0 0 892.7 159.83
-f32acc64 16 512 0 839.4 158.97
-f32acc64 16 768 0 887.8 159.03
-f32acc64 16 1024 0 902.5 159.09
-f32acc64 24 0 0 878.4 153.99
-f32acc64 24 512 0 850.9 153.45
-f32acc64 24 768 0 886.2 153.50
-f32acc64 24 1024 0 898.0 153.56
-f32acc64 32 0 0 869.2 150.93
-f32acc64 32 512 0 847.2 150.55
-f32acc64 32 768 0 879.6 150.61
+f32acc64 16 0 0 893.4 159.83
+f32acc64 16 512 0 840.3 158.97
+f32acc64 16 768 0 889.3 159.03
+f32acc64 16 1024 0 904.1 159.09
+f32acc64 24 0 0 879.6 153.99
+f32acc64 24 512 0 851.1 153.45
+f32acc64 24 768 0 885.5 153.50
+f32acc64 24 1024 0 899.1 153.56
+f32acc64 32 0 0 870.5 150.93
+f32acc64 32 512 0 849.6 150.55
+f32acc64 32 768 0 879.5 150.61
 f32acc64 32 1024 0 890.7 150.67
-f32acc64 48 0 0 865.3 148.01
-f32acc64 48 512 0 849.2 147.79
-f32acc64 48 768 0 870.6 147.85
-f32acc64 48 1024 0 879.7 147.90
-f32acc64 64 0 0 869.1 146.48
-f32acc64 64 512 0 845.1 146.34
+f32acc64 48 0 0 865.5 148.01
+f32acc64 48 512 0 850.5 147.79
+f32acc64 48 768 0 872.4 147.85
+f32acc64 48 1024 0 880.5 147.90
+f32acc64 64 0 0 866.9 146.48
+f32acc64 64 512 0 844.3 146.34
 f32acc64 64 768 0 860.9 146.40
-f32acc64 64 1024 0 869.1 146.45
-f32acc64 16 0 1 2594.5 163.42
-f32acc64 16 512 1 1149.5 162.56
-f32acc64 16 768 1 1585.6 162.62
-f32acc64 16 1024 1 2218.8 162.67
-f32acc64 24 0 1 2512.5 157.53
-f32acc64 24 512 1 1118.3 156.99
-f32acc64 24 768 1 1509.4 157.04
-f32acc64 24 1024 1 2210.2 157.10
-f32acc64 32 0 1 2423.1 154.44
-f32acc64 32 512 1 1101.9 154.07
-f32acc64 32 768 1 1476.7 154.12
-f32acc64 32 1024 1 2110.6 154.18
-f32acc64 48 0 1 2399.1 151.49
-f32acc64 48 512 1 1088.4 151.28
-f32acc64 48 768 1 1452.7 151.34
-f32acc64 48 1024 1 1835.2 151.39
-f32acc64 64 0 1 2368.0 149.95
-f32acc64 64 512 1 1065.3 149.82
-f32acc64 64 768 1 1305.8 149.88
-f32acc64 64 1024 1 2075.7 149.93
-f32acc64 36 0 0 869.1 149.95
-f32acc64 36 0 1 2251.6 153.46
-f64 16 0 0 1342.1 181.66
-f64 16 512 0 1328.1 180.37
-f64 16 768 0 1354.9 180.46
-f64 16 1024 0 1370.1 180.54
-f64 24 0 0 1312.7 174.80
-f64 24 512 0 1313.8 173.99
-f64 24 768 0 1331.4 174.07
-f64 24 1024 0 1326.0 174.16
-f64 32 0 0 1298.0 171.21
-f64 32 512 0 1312.2 170.65
-f64 32 768 0 1327.2 170.73
-f64 32 1024 0 1319.9 170.81
-f64 48 0 0 1289.0 167.78
-f64 48 512 0 1296.0 167.46
-f64 48 768 0 1307.4 167.54
-f64 48 1024 0 1308.5 167.62
-f64 64 0 0 1283.5 165.98
-f64 64 512 0 1302.5 165.78
-f64 64 768 0 1308.6 165.87
-f64 64 1024 0 1292.1 165.95
-f64 16 0 1 1341.3 181.66
-f64 16 512 1 1331.3 180.45
-f64 16 768 1 1353.7 180.53
-f64 16 1024 1 1366.9 180.60
-f64 24 0 1 1312.3 174.86
-f64 24 512 1 1306.1 174.10
-f64 24 768 1 1321.5 174.18
-f64 24 1024 1 1317.7 174.26
-f64 32 0 1 1296.2 171.30
-f64 32 512 1 1300.7 170.78
+f32acc64 64 1024 0 868.9 146.45
+f32acc64 16 0 1 2593.1 163.42
+f32acc64 16 512 1 1148.5 162.56
+f32acc64 16 768 1 1584.6 162.62
+f32acc64 16 1024 1 2217.8 162.67
+f32acc64 24 0 1 2510.8 157.53
+f32acc64 24 512 1 1117.5 156.99
+f32acc64 24 768 1 1507.6 157.04
+f32acc64 24 1024 1 2211.2 157.10
+f32acc64 32 0 1 2419.9 154.44
+f32acc64 32 512 1 1100.1 154.07
+f32acc64 32 768 1 1474.3 154.12
+f32acc64 32 1024 1 2111.2 154.18
+f32acc64 48 0 1 2403.9 151.49
+f32acc64 48 512 1 1086.9 151.28
+f32acc64 48 768 1 1448.3 151.34
+f32acc64 48 1024 1 1834.1 151.39
+f32acc64 64 0 1 2366.2 149.95
+f32acc64 64 512 1 1063.6 149.82
+f32acc64 64 768 1 1304.0 149.88
+f32acc64 64 1024 1 2079.4 149.93
+f32acc64 36 0 0 868.9 149.95
+f32acc64 36 0 1 2251.4 153.46
+f64 16 0 0 1342.6 181.66
+f64 16 512 0 1329.4 180.37
+f64 16 768 0 1355.5 180.46
+f64 16 1024 0 1367.8 180.54
+f64 24 0 0 1312.5 174.80
+f64 24 512 0 1311.0 173.99
+f64 24 768 0 1329.2 174.07
+f64 24 1024 0 1324.3 174.16
+f64 32 0 0 1297.6 171.21
+f64 32 512 0 1312.3 170.65
+f64 32 768 0 1326.7 170.73
+f64 32 1024 0 1318.6 170.81
+f64 48 0 0 1287.8 167.78
+f64 48 512 0 1300.8 167.46
+f64 48 768 0 1309.3 167.54
+f64 48 1024 0 1310.1 167.62
+f64 64 0 0 1283.8 165.98
+f64 64 512 0 1304.8 165.78
+f64 64 768 0 1305.8 165.87
+f64 64 1024 0 1291.7 165.95
+f64 16 0 1 1341.2 181.66
+f64 16 512 1 1330.6 180.45
+f64 16 768 1 1353.9 180.53
+f64 16 1024 1 1365.4 180.60
+f64 24 0 1 1312.1 174.86
+f64 24 512 1 1304.6 174.10
+f64 24 768 1 1320.4 174.18
+f64 24 1024 1 1315.9 174.26
+f64 32 0 1 1295.8 171.30
+f64 32 512 1 1296.3 170.78
 f64 32 768 1 1311.4 170.85
-f64 32 1024 1 1310.3 170.93
-f64 48 0 1 1280.4 167.91
-f64 48 512 1 1279.2 167.60
-f64 48 768 1 1295.4 167.68
-f64 48 1024 1 1296.0 167.76
-f64 64 0 1 1276.8 166.13
-f64 64 512 1 1284.4 165.94
-f64 64 768 1 1288.2 166.02
-f64 64 1024 1 1281.7 166.10
-f64 36 0 0 1294.6 170.06
+f64 32 1024 1 1310.6 170.93
+f64 48 0 1 1282.7 167.91
+f64 48 512 1 1281.9 167.60
+f64 48 768 1 1294.9 167.68
+f64 48 1024 1 1294.8 167.76
+f64 64 0 1 1275.9 166.13
+f64 64 512 1 1287.0 165.94
+f64 64 768 1 1290.3 166.02
+f64 64 1024 1 1280.9 166.10
+f64 36 0 0 1294.1 170.06
 f64 36 0 1 1291.6 170.17
 f32acc64_characteristic 16 0 0 802.2 376.78
-f32acc64_characteristic 16 512 0 839.8 375.44
-f32acc64_characteristic 16 768 0 862.9 375.52
-f32acc64_characteristic 16 1024 0 867.2 375.61
-f32acc64_characteristic 24 0 0 822.2 364.12
+f32acc64_characteristic 16 512 0 839.9 375.44
+f32acc64_characteristic 16 768 0 863.1 375.52
+f32acc64_characteristic 16 1024 0 866.8 375.61
+f32acc64_characteristic 24 0 0 822.1 364.12
 f32acc64_characteristic 24 512 0 818.4 363.27
-f32acc64_characteristic 24 768 0 839.2 363.36
-f32acc64_characteristic 24 1024 0 835.6 363.44
-f32acc64_characteristic 32 0 0 814.3 357.48
+f32acc64_characteristic 24 768 0 839.1 363.36
+f32acc64_characteristic 24 1024 0 835.4 363.44
+f32acc64_characteristic 32 0 0 814.5 357.48
 f32acc64_characteristic 32 512 0 810.5 356.90
 f32acc64_characteristic 32 768 0 828.3 356.98
-f32acc64_characteristic 32 1024 0 828.4 357.07
+f32acc64_characteristic 32 1024 0 828.5 357.07
 f32acc64_characteristic 48 0 0 805.9 351.15
 f32acc64_characteristic 48 512 0 808.3 350.82
 f32acc64_characteristic 48 768 0 812.8 350.90
-f32acc64_characteristic 48 1024 0 814.0 350.99
-f32acc64_characteristic 64 0 0 799.4 347.84
+f32acc64_characteristic 48 1024 0 814.1 350.99
+f32acc64_characteristic 64 0 0 799.6 347.84
 f32acc64_characteristic 64 512 0 800.3 347.63
 f32acc64_characteristic 64 768 0 802.0 347.72
-f32acc64_characteristic 64 1024 0 800.1 347.80
-f32acc64_characteristic 36 0 0 812.9 355.37
+f32acc64_characteristic 64 1024 0 800.0 347.80
+f32acc64_characteristic 36 0 0 813.0 355.37
 batched_1d 0 0 0 1857.3 146.83
-batched_1d 0 512 0 1858.1 137.20
+batched_1d 0 512 0 1858.2 137.20
 batched_1d 0 1024 0 1858.9 137.27
-batched_1d 0 2048 0 1861.1 137.41
+batched_1d 0 2048 0 1861.3 137.41
+batched_2d 16 0 0 22905.0 4867.90
+batched_2d 16 512 0 26963.5 4842.26
+batched_2d 16 768 0 26870.0 4842.32
+batched_2d 16 1024 0 27211.1 4842.37
+batched_2d 24 0 0 22649.3 4707.98
+batched_2d 24 512 0 26270.9 4690.82
+batched_2d 24 768 0 26286.3 4690.88
+batched_2d 24 1024 0 26564.1 4690.93
+batched_2d 32 0 0 22751.7 4628.36
+batched_2d 32 512 0 25953.8 4615.43
+batched_2d 32 768 0 25980.5 4615.49
+batched_2d 32 1024 0 26262.0 4615.54
+batched_2d 48 0 0 23083.3 4548.23
+batched_2d 48 512 0 25431.2 4539.55
+batched_2d 48 768 0 25577.5 4539.61
+batched_2d 48 1024 0 25911.6 4539.66
+batched_2d 64 0 0 23513.6 4508.28
+batched_2d 64 512 0 25070.7 4501.72
+batched_2d 64 768 0 25317.9 4501.78
+batched_2d 64 1024 0 25702.1 4501.83
+batched_2d 16 0 1 54996.9 4963.48
+batched_2d 16 512 1 31753.5 4938.31
+batched_2d 16 768 1 36893.3 4938.37
+batched_2d 16 1024 1 49136.2 4938.42
+batched_2d 24 0 1 54299.7 4801.74
+batched_2d 24 512 1 30365.7 4784.90
+batched_2d 24 768 1 35274.7 4784.95
+batched_2d 24 1024 1 47679.2 4785.01
+batched_2d 32 0 1 54206.1 4721.21
+batched_2d 32 512 1 29649.1 4708.52
+batched_2d 32 768 1 34350.9 4708.58
+batched_2d 32 1024 1 46901.5 4708.63
+batched_2d 48 0 1 54355.0 4640.17
+batched_2d 48 512 1 28832.4 4631.65
+batched_2d 48 768 1 33456.3 4631.71
+batched_2d 48 1024 1 46107.2 4631.76
+batched_2d 64 0 1 54551.5 4599.76
+batched_2d 64 512 1 28439.9 4593.33
+batched_2d 64 768 1 32994.6 4593.38
+batched_2d 64 1024 1 45459.0 4593.43
 """
 PROFILED = {(p, int(r), int(g), int(v)): (float(t) * 1e6, float(a) * 1e6)
             for p, r, g, v, t, a in (ln.split() for ln in _PROFILED_TABLE.strip().splitlines())}
@@ -514,11 +554,12 @@ def final_time_errors(hw, box, prec):
 def profile_candidates(hw, W):
     """One eagerly launched step per launch configuration the tuner can
     choose (`hweno_tuning_candidates`), for each benchmark path: the 2048^2
-    workload in F32_ACC64, FP64 and characteristic variables, and the
-    4096-problem 1D batch.  Prints the order as JSON lines (one untimed step
-    per path first, marked "warm"): under `rocprofv3 --pmc` the stage-kernel
-    dispatches come three per step in that order, which is how the
-    PROFILED table above was measured."""
+    workload in F32_ACC64, FP64 and characteristic variables, the
+    4096-problem 1D batch and the 256-problem 2D batch (F32_KAHAN).  Prints
+    the order as JSON lines (one untimed step per path first, marked
+    "warm"): under `rocprofv3 --pmc` the stage-kernel dispatches come three
+    per step in that order, which is how the PROFILED table above was
+    measured."""
     spec, st = W.quadrant_vortex_2d(2048, seed=7)
     for name, prec, charwise in (("f32acc64", hw.F32_ACC64, 0), ("f64", hw.F64, 0),
                                  ("f32acc64_characteristic", hw.F32_ACC64, 1)):
@@ -548,6 +589,20 @@ def profile_candidates(hw, W):
             h.step()
             h.sync()
             print(json.dumps(["batched_1d", 0, c.grid_blocks, c.variant]), flush=True)
+    entries = W.batched_2d(seed=11, nprob=256)
+    cfg = hw.default_config(2, precision=hw.F32_KAHAN, gauss_q=2, cfl=0.5)
+    with hw.Handle([e[0] for e in entries], cfg) as h:
+        for i, e in enumerate(entries):
+            h.set_state(i, W.batched_2d_state(e))
+        h.set_tuning(use_graph=0)
+        h.step()
+        h.sync()
+        print(json.dumps(["batched_2d", "warm"]), flush=True)
+        for c in h.tuning_candidates():
+            h.set_tuning(tile_rows=c.tile_rows, grid_blocks=c.grid_blocks, variant=c.variant)
+            h.step()
+            h.sync()
+            print(json.dumps(["batched_2d", c.tile_rows, c.grid_blocks, c.variant]), flush=True)
 
 
 def main():
