@@ -375,12 +375,6 @@ def bench_single(hw, W, O, spec, st, prec, charwise, args, dev, stream, threads,
         if O is not None:
             out["errors_first_step"] = first_step_errors(O, spec, st, cfg, gpu1, dt1, threads)
         del gpu1
-        if args.burn_in:
-            # the GPU idled while the host measured the oracle (or the
-            # process has just started): bring its clocks up before the
-            # first timed run
-            h.steps(args.burn_in)
-            torch.cuda.synchronize()
         runs = [] if (tune and args.profile_only) else [("default", None)]
         if tune:
             runs.append(("tuned", "autotune"))
@@ -395,6 +389,13 @@ def bench_single(hw, W, O, spec, st, prec, charwise, args, dev, stream, threads,
                 r["autotune_s"] = time.perf_counter() - t0
                 r["from_cache"] = bool(h.tuned_from_cache())
             r["tuning"] = tuning_dict(h.tuning())
+            if args.burn_in:
+                # the GPU idled while the host measured the oracle and while
+                # the state was uploaded: bring its clocks up before the
+                # timed run (so that the default and tuned launches are
+                # compared on equal terms)
+                h.steps(args.burn_in)
+                torch.cuda.synchronize()
             ms_step, wall, tm = timed_run(h, stream, args.steps, args.warmup)
             fin, t_now = h.get_state(0)
             r.update({"value": 3.0 * ncell / (ms_step * 1e-3), "ms_per_step": ms_step,
@@ -613,7 +614,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (baseline and errors)")
     ap.add_argument("--burn-in", type=int, default=200,
-                    help="untimed steps before a path's first measurement")
+                    help="untimed steps right before each timed 2048^2 run (after the state "
+                         "upload and the tuner), and before the batched runs' state upload")
     ap.add_argument("--no-tune", action="store_true", help="library defaults only")
     ap.add_argument("--launch", default=None,
                     help="ROWS,GRID,VARIANT: this launch configuration instead of the tuner's")
