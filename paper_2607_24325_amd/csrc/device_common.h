@@ -153,9 +153,12 @@ template <class T> struct Flux<T, F_EULER, 3, 0> {
         f[2] = u * Ep;
         const T dr = V[0], dm = V[1], dE = V[2];
         const T dp = gm1 * (dE - u * dm + half_u2 * dr);
+        // the rows of A V with the common factor a = dm - u dr taken out:
+        // 2u dm - u^2 dr = u (dm + a), H dm - u H dr = H a
+        const T a = dm - u * dr;
         fv[0] = dm;
-        fv[1] = (T)2 * u * dm - (T)2 * half_u2 * dr + dp;
-        fv[2] = H * dm + u * (dE + dp) - u * H * dr;
+        fv[1] = u * (dm + a) + dp;
+        fv[2] = H * a + u * (dE + dp);
     }
 };
 
@@ -163,19 +166,25 @@ template <class T> struct Flux<T, F_EULER, 3, 0> {
 template <class T, int DIR> struct Flux<T, F_EULER, 4, DIR> {
     T gm1;
     __device__ Flux(const Scheme& s) : gm1((T)(s.gas_gamma - 1.0)) {}
+    // (dF/dU) D or (dG/dU) D, with the common factor of three of its rows
+    // taken out: for F, a = dm - u dr gives 2u dm - u^2 dr = u (dm + a),
+    // v dm + u dn - uv dr = v a + u dn and H dm - uH dr = H a (for G
+    // likewise with b = dn - v dr)
     __device__ __forceinline__ void jvp(T u, T v, T q2h, T H, const T* D, T* out) const {
         const T dr = D[0], dm = D[1], dn = D[2], dE = D[3];
         const T dp = gm1 * (dE - u * dm - v * dn + q2h * dr);
         if (DIR == 0) {
+            const T a = dm - u * dr;
             out[0] = dm;
-            out[1] = (T)2 * u * dm - u * u * dr + dp;
-            out[2] = v * dm + u * dn - u * v * dr;
-            out[3] = H * dm + u * (dE + dp) - u * H * dr;
+            out[1] = u * (dm + a) + dp;
+            out[2] = v * a + u * dn;
+            out[3] = H * a + u * (dE + dp);
         } else {
+            const T b = dn - v * dr;
             out[0] = dn;
-            out[1] = v * dm + u * dn - u * v * dr;
-            out[2] = (T)2 * v * dn - v * v * dr + dp;
-            out[3] = H * dn + v * (dE + dp) - v * H * dr;
+            out[1] = u * b + v * dm;
+            out[2] = v * (dn + b) + dp;
+            out[3] = H * b + v * (dE + dp);
         }
     }
     // velocity, half its square, pressure and total enthalpy of U
