@@ -42,161 +42,161 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # kernel sources of this hash; any change of the sources
 # invalidates them, and a configuration not profiled has none (both are
 # reported as null).
-PROFILED_SOURCES = "4a94129bb35d6191"
+PROFILED_SOURCES = "12f6670ea8fd1413"
 # path, tile_rows, grid_blocks, variant: HBM MB and VALU wave-instructions (M)
 # per stage launch, mean of the three stages, for every launch configuration
 # the tuner can choose (one eager step each; 2048^2 workload, 4096-problem 1D
 # batch, where segment heights do not apply, 256-problem 2D batch)
 _PROFILED_TABLE = """
-f32acc64 16 0 0 893.4 159.83
-f32acc64 16 512 0 840.3 158.97
-f32acc64 16 768 0 889.3 159.03
-f32acc64 16 1024 0 904.1 159.09
-f32acc64 24 0 0 879.6 153.99
-f32acc64 24 512 0 851.1 153.45
-f32acc64 24 768 0 885.5 153.50
-f32acc64 24 1024 0 899.1 153.56
-f32acc64 32 0 0 870.5 150.93
-f32acc64 32 512 0 849.6 150.55
-f32acc64 32 768 0 879.5 150.61
-f32acc64 32 1024 0 890.7 150.67
-f32acc64 48 0 0 865.5 148.01
-f32acc64 48 512 0 850.5 147.79
-f32acc64 48 768 0 872.4 147.85
-f32acc64 48 1024 0 880.5 147.90
-f32acc64 64 0 0 866.9 146.48
-f32acc64 64 512 0 844.3 146.34
-f32acc64 64 768 0 860.9 146.40
-f32acc64 64 1024 0 868.9 146.45
-f32acc64 16 0 1 2593.1 163.42
-f32acc64 16 512 1 1148.5 162.56
-f32acc64 16 768 1 1584.6 162.62
-f32acc64 16 1024 1 2217.8 162.67
-f32acc64 24 0 1 2510.8 157.53
-f32acc64 24 512 1 1117.5 156.99
-f32acc64 24 768 1 1507.6 157.04
-f32acc64 24 1024 1 2211.2 157.10
-f32acc64 32 0 1 2419.9 154.44
-f32acc64 32 512 1 1100.1 154.07
-f32acc64 32 768 1 1474.3 154.12
-f32acc64 32 1024 1 2111.2 154.18
-f32acc64 48 0 1 2403.9 151.49
-f32acc64 48 512 1 1086.9 151.28
-f32acc64 48 768 1 1448.3 151.34
-f32acc64 48 1024 1 1834.1 151.39
-f32acc64 64 0 1 2366.2 149.95
-f32acc64 64 512 1 1063.6 149.82
-f32acc64 64 768 1 1304.0 149.88
-f32acc64 64 1024 1 2079.4 149.93
-f32acc64 36 0 0 868.9 149.95
-f32acc64 36 0 1 2251.4 153.46
-f64 16 0 0 1342.6 181.66
-f64 16 512 0 1329.4 180.37
-f64 16 768 0 1355.5 180.46
-f64 16 1024 0 1367.8 180.54
-f64 24 0 0 1312.5 174.80
-f64 24 512 0 1311.0 173.99
-f64 24 768 0 1329.2 174.07
-f64 24 1024 0 1324.3 174.16
-f64 32 0 0 1297.6 171.21
-f64 32 512 0 1312.3 170.65
-f64 32 768 0 1326.7 170.73
-f64 32 1024 0 1318.6 170.81
-f64 48 0 0 1287.8 167.78
-f64 48 512 0 1300.8 167.46
-f64 48 768 0 1309.3 167.54
-f64 48 1024 0 1310.1 167.62
-f64 64 0 0 1283.8 165.98
-f64 64 512 0 1304.8 165.78
-f64 64 768 0 1305.8 165.87
-f64 64 1024 0 1291.7 165.95
-f64 16 0 1 1341.2 181.66
-f64 16 512 1 1330.6 180.45
-f64 16 768 1 1353.9 180.53
-f64 16 1024 1 1365.4 180.60
-f64 24 0 1 1312.1 174.86
-f64 24 512 1 1304.6 174.10
-f64 24 768 1 1320.4 174.18
-f64 24 1024 1 1315.9 174.26
-f64 32 0 1 1295.8 171.30
-f64 32 512 1 1296.3 170.78
-f64 32 768 1 1311.4 170.85
-f64 32 1024 1 1310.6 170.93
-f64 48 0 1 1282.7 167.91
-f64 48 512 1 1281.9 167.60
-f64 48 768 1 1294.9 167.68
-f64 48 1024 1 1294.8 167.76
-f64 64 0 1 1275.9 166.13
-f64 64 512 1 1287.0 165.94
-f64 64 768 1 1290.3 166.02
-f64 64 1024 1 1280.9 166.10
-f64 36 0 0 1294.1 170.06
-f64 36 0 1 1291.6 170.17
-f32acc64_characteristic 16 0 0 802.2 376.78
-f32acc64_characteristic 16 512 0 839.9 375.44
-f32acc64_characteristic 16 768 0 863.1 375.52
-f32acc64_characteristic 16 1024 0 866.8 375.61
-f32acc64_characteristic 24 0 0 822.1 364.12
-f32acc64_characteristic 24 512 0 818.4 363.27
-f32acc64_characteristic 24 768 0 839.1 363.36
-f32acc64_characteristic 24 1024 0 835.4 363.44
-f32acc64_characteristic 32 0 0 814.5 357.48
-f32acc64_characteristic 32 512 0 810.5 356.90
-f32acc64_characteristic 32 768 0 828.3 356.98
-f32acc64_characteristic 32 1024 0 828.5 357.07
-f32acc64_characteristic 48 0 0 805.9 351.15
-f32acc64_characteristic 48 512 0 808.3 350.82
-f32acc64_characteristic 48 768 0 812.8 350.90
-f32acc64_characteristic 48 1024 0 814.1 350.99
-f32acc64_characteristic 64 0 0 799.6 347.84
-f32acc64_characteristic 64 512 0 800.3 347.63
-f32acc64_characteristic 64 768 0 802.0 347.72
-f32acc64_characteristic 64 1024 0 800.0 347.80
-f32acc64_characteristic 36 0 0 813.0 355.37
-batched_1d 0 0 0 1857.3 146.83
-batched_1d 0 512 0 1858.2 137.20
-batched_1d 0 1024 0 1858.9 137.27
-batched_1d 0 2048 0 1861.3 137.41
-batched_2d 16 0 0 22905.0 4867.90
-batched_2d 16 512 0 26963.5 4842.26
-batched_2d 16 768 0 26870.0 4842.32
-batched_2d 16 1024 0 27211.1 4842.37
-batched_2d 24 0 0 22649.3 4707.98
-batched_2d 24 512 0 26270.9 4690.82
-batched_2d 24 768 0 26286.3 4690.88
-batched_2d 24 1024 0 26564.1 4690.93
-batched_2d 32 0 0 22751.7 4628.36
-batched_2d 32 512 0 25953.8 4615.43
-batched_2d 32 768 0 25980.5 4615.49
-batched_2d 32 1024 0 26262.0 4615.54
-batched_2d 48 0 0 23083.3 4548.23
-batched_2d 48 512 0 25431.2 4539.55
-batched_2d 48 768 0 25577.5 4539.61
-batched_2d 48 1024 0 25911.6 4539.66
-batched_2d 64 0 0 23513.6 4508.28
-batched_2d 64 512 0 25070.7 4501.72
-batched_2d 64 768 0 25317.9 4501.78
-batched_2d 64 1024 0 25702.1 4501.83
-batched_2d 16 0 1 54996.9 4963.48
-batched_2d 16 512 1 31753.5 4938.31
-batched_2d 16 768 1 36893.3 4938.37
-batched_2d 16 1024 1 49136.2 4938.42
-batched_2d 24 0 1 54299.7 4801.74
-batched_2d 24 512 1 30365.7 4784.90
-batched_2d 24 768 1 35274.7 4784.95
-batched_2d 24 1024 1 47679.2 4785.01
-batched_2d 32 0 1 54206.1 4721.21
-batched_2d 32 512 1 29649.1 4708.52
-batched_2d 32 768 1 34350.9 4708.58
-batched_2d 32 1024 1 46901.5 4708.63
-batched_2d 48 0 1 54355.0 4640.17
-batched_2d 48 512 1 28832.4 4631.65
-batched_2d 48 768 1 33456.3 4631.71
-batched_2d 48 1024 1 46107.2 4631.76
-batched_2d 64 0 1 54551.5 4599.76
-batched_2d 64 512 1 28439.9 4593.33
-batched_2d 64 768 1 32994.6 4593.38
-batched_2d 64 1024 1 45459.0 4593.43
+f32acc64 16 0 0 893.7 156.70
+f32acc64 16 512 0 840.4 155.83
+f32acc64 16 768 0 888.3 155.89
+f32acc64 16 1024 0 904.8 155.94
+f32acc64 24 0 0 878.7 150.91
+f32acc64 24 512 0 850.1 150.37
+f32acc64 24 768 0 884.3 150.42
+f32acc64 24 1024 0 897.1 150.48
+f32acc64 32 0 0 870.3 147.88
+f32acc64 32 512 0 849.8 147.50
+f32acc64 32 768 0 877.1 147.56
+f32acc64 32 1024 0 894.1 147.61
+f32acc64 48 0 0 865.6 144.99
+f32acc64 48 512 0 850.7 144.77
+f32acc64 48 768 0 871.2 144.82
+f32acc64 48 1024 0 882.4 144.88
+f32acc64 64 0 0 866.9 143.47
+f32acc64 64 512 0 845.6 143.34
+f32acc64 64 768 0 859.2 143.39
+f32acc64 64 1024 0 870.0 143.45
+f32acc64 16 0 1 2349.0 159.98
+f32acc64 16 512 1 1101.0 159.13
+f32acc64 16 768 1 1608.1 159.18
+f32acc64 16 1024 1 2184.5 159.24
+f32acc64 24 0 1 2320.8 154.15
+f32acc64 24 512 1 1053.0 153.62
+f32acc64 24 768 1 1535.8 153.67
+f32acc64 24 1024 1 2170.2 153.73
+f32acc64 32 0 1 2281.0 151.10
+f32acc64 32 512 1 1032.5 150.73
+f32acc64 32 768 1 1508.2 150.78
+f32acc64 32 1024 1 2082.7 150.84
+f32acc64 48 0 1 2202.1 148.18
+f32acc64 48 512 1 1019.2 147.97
+f32acc64 48 768 1 1467.5 148.02
+f32acc64 48 1024 1 1805.9 148.08
+f32acc64 64 0 1 2236.1 146.66
+f32acc64 64 512 1 1001.5 146.53
+f32acc64 64 768 1 1353.1 146.58
+f32acc64 64 1024 1 2048.3 146.64
+f32acc64 36 0 0 869.5 146.91
+f32acc64 36 0 1 2099.0 150.13
+f64 16 0 0 1342.3 178.61
+f64 16 512 0 1331.7 177.33
+f64 16 768 0 1355.1 177.41
+f64 16 1024 0 1368.5 177.49
+f64 24 0 0 1312.9 171.81
+f64 24 512 0 1313.8 171.00
+f64 24 768 0 1329.5 171.09
+f64 24 1024 0 1323.7 171.17
+f64 32 0 0 1296.9 168.25
+f64 32 512 0 1317.1 167.69
+f64 32 768 0 1324.5 167.77
+f64 32 1024 0 1319.5 167.86
+f64 48 0 0 1286.7 164.85
+f64 48 512 0 1305.2 164.53
+f64 48 768 0 1306.9 164.61
+f64 48 1024 0 1309.9 164.69
+f64 64 0 0 1283.0 163.07
+f64 64 512 0 1306.8 162.87
+f64 64 768 0 1304.1 162.96
+f64 64 1024 0 1287.2 163.04
+f64 16 0 1 1341.2 178.91
+f64 16 512 1 1333.7 177.65
+f64 16 768 1 1358.0 177.73
+f64 16 1024 1 1368.8 177.81
+f64 24 0 1 1313.6 172.14
+f64 24 512 1 1313.9 171.34
+f64 24 768 1 1330.5 171.42
+f64 24 1024 1 1321.3 171.51
+f64 32 0 1 1297.5 168.59
+f64 32 512 1 1313.1 168.04
+f64 32 768 1 1323.7 168.12
+f64 32 1024 1 1318.9 168.20
+f64 48 0 1 1286.9 165.20
+f64 48 512 1 1300.6 164.89
+f64 48 768 1 1307.3 164.97
+f64 48 1024 1 1311.1 165.05
+f64 64 0 1 1284.8 163.43
+f64 64 512 1 1304.0 163.24
+f64 64 768 1 1304.2 163.32
+f64 64 1024 1 1291.2 163.40
+f64 36 0 0 1294.1 167.12
+f64 36 0 1 1293.8 167.46
+f32acc64_characteristic 16 0 0 801.8 373.73
+f32acc64_characteristic 16 512 0 839.2 372.39
+f32acc64_characteristic 16 768 0 862.6 372.48
+f32acc64_characteristic 16 1024 0 867.9 372.56
+f32acc64_characteristic 24 0 0 821.8 361.13
+f32acc64_characteristic 24 512 0 817.9 360.28
+f32acc64_characteristic 24 768 0 839.4 360.37
+f32acc64_characteristic 24 1024 0 835.9 360.46
+f32acc64_characteristic 32 0 0 814.2 354.53
+f32acc64_characteristic 32 512 0 810.7 353.94
+f32acc64_characteristic 32 768 0 828.3 354.03
+f32acc64_characteristic 32 1024 0 828.5 354.11
+f32acc64_characteristic 48 0 0 805.9 348.22
+f32acc64_characteristic 48 512 0 808.0 347.89
+f32acc64_characteristic 48 768 0 812.7 347.97
+f32acc64_characteristic 48 1024 0 814.0 348.06
+f32acc64_characteristic 64 0 0 799.5 344.92
+f32acc64_characteristic 64 512 0 800.2 344.72
+f32acc64_characteristic 64 768 0 801.9 344.80
+f32acc64_characteristic 64 1024 0 800.1 344.89
+f32acc64_characteristic 36 0 0 812.9 352.43
+batched_1d 0 0 0 1857.4 145.15
+batched_1d 0 512 0 1858.0 135.52
+batched_1d 0 1024 0 1858.9 135.59
+batched_1d 0 2048 0 1861.0 135.73
+batched_2d 16 0 0 22914.4 4788.12
+batched_2d 16 512 0 27014.1 4762.48
+batched_2d 16 768 0 26950.1 4762.53
+batched_2d 16 1024 0 27213.5 4762.59
+batched_2d 24 0 0 22661.0 4629.75
+batched_2d 24 512 0 26289.6 4612.60
+batched_2d 24 768 0 26394.3 4612.66
+batched_2d 24 1024 0 26601.3 4612.71
+batched_2d 32 0 0 22756.4 4550.91
+batched_2d 32 512 0 26031.2 4537.99
+batched_2d 32 768 0 26139.6 4538.04
+batched_2d 32 1024 0 26378.1 4538.10
+batched_2d 48 0 0 23088.0 4471.57
+batched_2d 48 512 0 25638.5 4462.89
+batched_2d 48 768 0 25739.1 4462.95
+batched_2d 48 1024 0 25911.7 4463.00
+batched_2d 64 0 0 23545.5 4432.00
+batched_2d 64 512 0 25143.9 4425.45
+batched_2d 64 768 0 25516.7 4425.50
+batched_2d 64 1024 0 25782.4 4425.56
+batched_2d 16 0 1 52423.3 4803.91
+batched_2d 16 512 1 31315.1 4778.75
+batched_2d 16 768 1 41837.8 4778.80
+batched_2d 16 1024 1 55597.2 4778.86
+batched_2d 24 0 1 51582.9 4645.29
+batched_2d 24 512 1 29843.7 4628.46
+batched_2d 24 768 1 40691.1 4628.51
+batched_2d 24 1024 1 54362.9 4628.57
+batched_2d 32 0 1 51334.6 4566.32
+batched_2d 32 512 1 29146.4 4553.63
+batched_2d 32 768 1 39965.0 4553.69
+batched_2d 32 1024 1 53750.0 4553.74
+batched_2d 48 0 1 51366.1 4486.85
+batched_2d 48 512 1 28322.5 4478.33
+batched_2d 48 768 1 39269.2 4478.38
+batched_2d 48 1024 1 53096.4 4478.44
+batched_2d 64 0 1 51527.3 4447.22
+batched_2d 64 512 1 27901.3 4440.78
+batched_2d 64 768 1 38862.9 4440.84
+batched_2d 64 1024 1 52380.7 4440.89
 """
 PROFILED = {(p, int(r), int(g), int(v)): (float(t) * 1e6, float(a) * 1e6)
             for p, r, g, v, t, a in (ln.split() for ln in _PROFILED_TABLE.strip().splitlines())}
