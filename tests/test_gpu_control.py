@@ -178,3 +178,32 @@ def test_steps_equal_single_steps(graph):
     ref, n = O.run(oproblem(spec1, cfg), s1, 0.0, spec1.t_end, CFL)
     assert n < 19
     assert scaled_err(finals[0][1][0], ref, natural_scales(spec1, s1)) < 1e-10
+
+
+def test_profiled_counters_cover_every_tuner_candidate():
+    """The bench line's measured traffic comes from a table of counters
+    (bench.py's PROFILED) taken for every launch configuration the tuner can
+    choose; while the kernel sources are the profiled ones, every candidate
+    hweno_tuning_candidates lists for the benchmark workloads must be in it,
+    or the line would report no traffic for that choice."""
+    import bench
+    if bench.kernel_sources_hash() != bench.PROFILED_SOURCES:
+        pytest.skip("kernel sources changed since the counters were taken")
+    import dataclasses
+    spec, _ = W.quadrant_vortex_2d(64, seed=7)
+    specs2d = [dataclasses.replace(spec, nx=2048, ny=2048)]   # the benchmark's size
+    missing = []
+    for name, prec, charwise in (("f32acc64", hw.F32_ACC64, 0), ("f64", hw.F64, 0),
+                                 ("f32acc64_characteristic", hw.F32_ACC64, 1)):
+        cfg = hw.default_config(2, precision=prec, gauss_q=2, cfl=0.5, characteristic=charwise)
+        with hw.Handle(specs2d, cfg) as h:
+            for c in h.tuning_candidates():
+                key = (name, c.tile_rows, c.grid_blocks, c.variant)
+                if key not in bench.PROFILED:
+                    missing.append(key)
+    entries = W.batched_1d(seed=1, nprob=4096)
+    with hw.Handle([e[0] for e in entries], hw.default_config(1, precision=hw.F32_ACC64)) as h:
+        for c in h.tuning_candidates():
+            if ("batched_1d", 0, c.grid_blocks, c.variant) not in bench.PROFILED:
+                missing.append(("batched_1d", c.grid_blocks, c.variant))
+    assert not missing, missing
